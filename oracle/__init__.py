@@ -1,0 +1,249 @@
+"""FP64 CPU oracle for the tensor-tomography hot path (test infrastructure).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the benchmark's
+CPU-baseline leg use this package.  It wraps ``tt_oracle.c`` (plain C, FP64,
+written from the paper's equations) through ctypes and shares nothing with the
+GPU library.  See ``tt_oracle.c`` for the equations each function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Private volumes of the threaded adjoint are limited to this many bytes.
+MEM_BUDGET = float(os.environ.get("TT_ORACLE_MEM", 8e9))
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the host C compiler (gcc -O2 -fopenmp)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Geom(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("ell_max", C.c_int32), ("n_proj", C.c_int32),
+        ("nj", C.c_int32), ("nk", C.c_int32), ("n_seg", C.c_int32), ("n_sub", C.c_int32),
+        ("reserved", C.c_int32),
+        ("step", C.c_double), ("seg_span", C.c_double),
+        ("inner", _dp), ("outer", _dp), ("joff", _dp), ("koff", _dp),
+        ("p", C.c_double * 3), ("j", C.c_double * 3), ("k", C.c_double * 3),
+        ("q0", C.c_double * 3), ("q90", C.c_double * 3),
+        ("alpha", C.c_double * 3), ("beta", C.c_double * 3),
+    ]
+
+
+def _declare(L):
+    L.og_num_coeffs.argtypes = [C.c_int]
+    L.og_num_coeffs.restype = C.c_int
+    L.og_legendre.argtypes = [C.c_int, C.c_int, C.c_double]
+    L.og_legendre.restype = C.c_double
+    L.og_sh_batch.argtypes = [C.c_int, C.c_int64, _dp, _dp]
+    L.og_rotation.argtypes = [C.POINTER(Geom), C.c_int, _dp]
+    L.og_projection_frame.argtypes = [C.POINTER(Geom), C.c_int, _dp]
+    L.og_basis_matrix.argtypes = [C.POINTER(Geom), _dp]
+    L.og_project.argtypes = [C.POINTER(Geom), _dp, _dp, _dp]
+    L.og_project_rays.argtypes = [C.POINTER(Geom), _dp, _dp, C.c_int64, _ip, _dp]
+    L.og_adjoint.argtypes = [C.POINTER(Geom), _dp, _dp, _dp, C.c_double]
+    L.og_adjoint_voxels.argtypes = [C.POINTER(Geom), _dp, _dp, C.c_int64, _ip, _dp]
+    L.og_loss_grad.argtypes = [C.POINTER(Geom), _dp, _dp, _dp, _dp, C.c_double, _dp, _dp,
+                               C.c_double]
+    L.og_loss_grad.restype = C.c_double
+    L.og_lbfgs.argtypes = [C.POINTER(Geom), _dp, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int,
+                           C.c_double, _dp, _dp, C.c_double]
+    L.og_lbfgs.restype = C.c_int
+    L.og_max_threads.restype = C.c_int
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_coeffs(ell_max: int) -> int:
+    return (ell_max // 2 + 1) * (ell_max + 1)
+
+
+def max_threads() -> int:
+    return lib().og_max_threads()
+
+
+class Geometry:
+    """Acquisition geometry; keeps the angle arrays alive for the C struct."""
+
+    def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame, n_sub=3, step=1.0,
+                 seg_span=2 * np.pi, joff=None, koff=None):
+        self.n = tuple(int(v) for v in n)
+        self.ell_max = int(ell_max)
+        self.inner = _f64(inner)
+        self.outer = _f64(outer)
+        self.joff = None if joff is None else _f64(joff)
+        self.koff = None if koff is None else _f64(koff)
+        self.nj, self.nk, self.n_seg, self.n_sub = int(nj), int(nk), int(n_seg), int(n_sub)
+        self.step, self.seg_span = float(step), float(seg_span)
+        self.frame = {k: tuple(float(x) for x in v) for k, v in frame.items()}
+        g = Geom()
+        g.nx, g.ny, g.nz = self.n
+        g.ell_max = self.ell_max
+        g.n_proj = len(self.inner)
+        g.nj, g.nk, g.n_seg, g.n_sub = self.nj, self.nk, self.n_seg, self.n_sub
+        g.step, g.seg_span = self.step, self.seg_span
+        g.inner, g.outer = _p(self.inner), _p(self.outer)
+        g.joff, g.koff = _p(self.joff), _p(self.koff)
+        for name, field in (("p", "p"), ("j", "j"), ("k", "k"), ("q0", "q0"), ("q90", "q90"),
+                            ("alpha", "alpha"), ("beta", "beta")):
+            getattr(g, field)[:] = self.frame[name]
+        self._g = g
+        self._B = None
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        from paper_2504_16446_amd import synth
+        inner, outer = synth.angles(w)
+        args = dict(n=w.n, ell_max=w.ell_max, inner=inner, outer=outer, nj=w.nj, nk=w.nk,
+                    n_seg=w.n_seg, frame=synth.lab_frame(), n_sub=w.n_sub, step=w.step)
+        args.update(kw)
+        return cls(**args)
+
+    @property
+    def n_proj(self):
+        return len(self.inner)
+
+    @property
+    def n_coeff(self):
+        return num_coeffs(self.ell_max)
+
+    @property
+    def vol_shape(self):
+        return self.n + (self.n_coeff,)
+
+    @property
+    def data_shape(self):
+        return (self.n_proj, self.nj, self.nk, self.n_seg)
+
+    def ref(self):
+        return C.byref(self._g)
+
+    def B(self):
+        if self._B is None:
+            self._B = basis_matrix(self)
+        return self._B
+
+
+def legendre(l, m, x):
+    return lib().og_legendre(int(l), int(m), float(x))
+
+
+def sh(ell_max, dirs):
+    d = _f64(dirs).reshape(-1, 3)
+    out = np.empty((d.shape[0], num_coeffs(ell_max)))
+    lib().og_sh_batch(int(ell_max), d.shape[0], _p(d), _p(out))
+    return out.reshape(np.shape(dirs)[:-1] + (num_coeffs(ell_max),))
+
+
+def rotation(g: Geometry, s: int):
+    R = np.empty(9)
+    lib().og_rotation(g.ref(), int(s), _p(R))
+    return R.reshape(3, 3)
+
+
+def frame(g: Geometry, s: int):
+    """(e_j, e_k, d, o) of projection s in centred sample coordinates."""
+    f = np.empty(12)
+    lib().og_projection_frame(g.ref(), int(s), _p(f))
+    return f[0:3], f[3:6], f[6:9], f[9:12]
+
+
+def basis_matrix(g: Geometry):
+    B = np.empty((g.n_proj, g.n_seg, g.n_coeff))
+    lib().og_basis_matrix(g.ref(), _p(B))
+    return B
+
+
+def project(g: Geometry, c):
+    c = _f64(c)
+    assert c.shape == g.vol_shape, (c.shape, g.vol_shape)
+    out = np.empty(g.data_shape)
+    lib().og_project(g.ref(), _p(g.B()), _p(c), _p(out))
+    return out
+
+
+def project_rays(g: Geometry, c, sjk):
+    c = _f64(c)
+    idx = np.ascontiguousarray(sjk, dtype=np.int32).reshape(-1, 3)
+    out = np.empty((idx.shape[0], g.n_seg))
+    lib().og_project_rays(g.ref(), _p(g.B()), _p(c), idx.shape[0],
+                          idx.ctypes.data_as(_ip), _p(out))
+    return out
+
+
+def adjoint(g: Geometry, y):
+    y = _f64(y)
+    assert y.shape == g.data_shape, (y.shape, g.data_shape)
+    out = np.empty(g.vol_shape)
+    lib().og_adjoint(g.ref(), _p(g.B()), _p(y), _p(out), MEM_BUDGET)
+    return out
+
+
+def adjoint_voxels(g: Geometry, y, xyz):
+    y = _f64(y)
+    idx = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    out = np.empty((idx.shape[0], g.n_coeff))
+    lib().og_adjoint_voxels(g.ref(), _p(g.B()), _p(y), idx.shape[0],
+                            idx.ctypes.data_as(_ip), _p(out))
+    return out
+
+
+def loss_grad(g: Geometry, c, data, w=None, mu=0.0):
+    """(loss, grad, resid) of L = sum w (Ac - I)^2 + mu sum c^2."""
+    c, data = _f64(c), _f64(data)
+    w = None if w is None else _f64(w)
+    grad = np.empty(g.vol_shape)
+    resid = np.empty(g.data_shape)
+    loss = lib().og_loss_grad(g.ref(), _p(g.B()), _p(c), _p(data), _p(w), float(mu),
+                              _p(grad), _p(resid), MEM_BUDGET)
+    return loss, grad, resid
+
+
+def lbfgs(g: Geometry, c0, data, w=None, mu=0.0, m=10, max_iter=10, tol=0.0):
+    """L-BFGS with exact line search.  Returns (c, iters, hist[iters,2], final_rel)."""
+    c = _f64(c0).copy()
+    data = _f64(data)
+    w = None if w is None else _f64(w)
+    hist = np.zeros((max(max_iter, 1), 2))
+    fr = C.c_double(0.0)
+    it = lib().og_lbfgs(g.ref(), _p(g.B()), _p(c), _p(data), _p(w), float(mu), int(m),
+                        int(max_iter), float(tol), _p(hist), C.byref(fr), MEM_BUDGET)
+    return c, it, hist[:it], fr.value

@@ -1,0 +1,29 @@
+"""Small acquisition geometries used across the test-suite."""
+import numpy as np
+
+import oracle
+from paper_2504_16446_amd import synth
+
+
+def tilted_angles(n_rot, tilts_deg, span_deg=180.0, phase_deg=7.0):
+    rot = phase_deg + np.arange(n_rot) * span_deg / n_rot
+    inner = np.deg2rad(np.tile(rot, len(tilts_deg)))
+    outer = np.deg2rad(np.repeat(np.asarray(tilts_deg, float), n_rot))
+    return inner, outer
+
+
+def tiny(ell_max=2, n=(6, 7, 8), nj=9, nk=10, n_seg=8, step=1.0, offsets=False):
+    inner, outer = tilted_angles(3, (0.0, 33.0))
+    kw = {}
+    if offsets:
+        kw = dict(joff=np.linspace(-0.4, 0.3, len(inner)), koff=np.linspace(0.25, -0.35, len(inner)))
+    return oracle.Geometry(n, ell_max, inner, outer, nj, nk, n_seg, synth.lab_frame(), step=step, **kw)
+
+
+def small(ell_max=4, n=(20, 24, 17), nj=23, nk=29, n_seg=8, n_rot=4, tilts=(0.0, 20.0, 45.0)):
+    inner, outer = tilted_angles(n_rot, tilts, span_deg=360.0)
+    return oracle.Geometry(n, ell_max, inner, outer, nj, nk, n_seg, synth.lab_frame())
+
+
+def workload(name, **kw):
+    return oracle.Geometry.from_workload(synth.WORKLOADS[name], **kw)
