@@ -1,0 +1,198 @@
+/*
+ * tt.h -- C ABI of the MI355X tensor-tomography hot path.
+ *
+ * The library computes the linear forward model of SAXS/WAXS tensor
+ * tomography of Nielsen et al. ("Mumott", section 2, Eqs. projection_matrix,
+ * real_space_geom, projection_operator and forward_model),
+ *
+ *     I_sjkc = sum_xyz P_{sjk,xyz} sum_i B_{sc,i} c_xyzi        (I = A c),
+ *
+ * its exact adjoint, the squared loss with L2 regularisation of
+ * Eq. opt_prob_general_form and its gradient, and an L-BFGS driver
+ * (section 3.5, "Optimization"), all on one gfx950 GPU.
+ *
+ * Discretisation (the paper leaves it open): P_{sjk,xyz} is unit-step ray
+ * sampling with trilinear weights and zero padding, samples at
+ * x_n = u_jk + n * step * d_s for integer n, each weighted by step; voxel and
+ * detector grids are centred on the rotation centre.  B_{sc,i} is the mean of
+ * the real even-order spherical harmonic Y_i(R_s^T q(phi)) over n_sub
+ * midpoint nodes of segment c, with the small-angle q(phi) of Eq. 1.
+ *
+ * Conventions for every call:
+ *  - Layouts are row-major, float32 unless stated:
+ *      coefficients c[nx][ny][nz][C],  C = (ell_max/2 + 1)(ell_max + 1),
+ *      data / residual I[n_proj][nj][nk][n_seg],
+ *      basis constants B[n_proj][n_seg][C] (float64, host).
+ *    Coefficient index i(l, m) = l(l-1)/2 + l + m for even l, m = -l..l.
+ *  - Pointers named *_dev are device pointers on the context's device; the
+ *    caller allocates and owns them.  A context owns only its own tables and
+ *    internal work buffers.
+ *  - Device work is enqueued on the context's stream (tt_set_stream) and is
+ *    asynchronous unless stated otherwise.  A context must not be used from
+ *    two host threads at once.
+ *  - Every int-returning call returns TT_OK (0) or a negative TT_E* code and
+ *    never aborts; tt_error_string() names the code and tt_last_error() gives
+ *    the message of the most recent failure on the calling thread.
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TT_OK = 0,
+    TT_EINVAL = -1,       /* null pointer or out-of-range argument */
+    TT_ESHAPE = -2,       /* inconsistent sizes */
+    TT_ENOMEM = -3,       /* device or host allocation failed */
+    TT_EHIP = -4,         /* a HIP runtime call failed */
+    TT_ENONFINITE = -5,   /* a reduction produced NaN or Inf */
+    TT_EUNSUPPORTED = -6  /* valid but not implemented (e.g. ell_max > 16) */
+};
+
+/* Precision of the coefficient-to-segment mapping. */
+enum { TT_MAP_FP32 = 0, TT_MAP_BF16 = 1 };
+
+/* Acquisition geometry (section 2, Table tab:geometry_vectors and
+ * Eq. real_space_geom).  Angle and offset arrays are host pointers read
+ * during tt_create only. */
+typedef struct tt_geometry {
+    int32_t nx, ny, nz;         /* volume shape, unit voxels (a = b = 1) */
+    int32_t ell_max;            /* even, 0..16 */
+    int32_t n_proj;             /* number of goniometer settings s */
+    int32_t nj, nk;             /* raster (detector pixel) grid */
+    int32_t n_seg;              /* azimuthal detector segments, 1..64 */
+    int32_t n_sub;              /* midpoint nodes per segment (>= 1) */
+    int32_t map_precision;      /* TT_MAP_FP32 or TT_MAP_BF16 */
+    double step;                /* ray sample spacing in voxels (> 0) */
+    double seg_span;            /* angle covered by the segments: 2 pi (WAXS) or pi */
+    const double *inner_angle;  /* alpha_s [rad], length n_proj */
+    const double *outer_angle;  /* beta_s [rad], length n_proj */
+    const double *j_offset;     /* delta j_s, length n_proj, or NULL for 0 */
+    const double *k_offset;     /* delta k_s, or NULL */
+    double p[3], j[3], k[3];    /* beam and raster directions, lab frame */
+    double q0[3], q90[3];       /* detector azimuth origin and +90 deg */
+    double alpha_axis[3];       /* inner (rotation) stage axis */
+    double beta_axis[3];        /* outer (tilt) stage axis */
+} tt_geometry;
+
+typedef struct tt_ctx tt_ctx;
+
+/* Build a context on the current HIP device: validates the geometry, computes
+ * R_s = R_beta(beta_s) R_alpha(alpha_s), the ray frames and B_{sc,i} in
+ * float64 on the host, uploads device tables and allocates work buffers.
+ * Synchronous.  On failure *out is NULL. */
+int tt_create(const tt_geometry *geom, tt_ctx **out);
+void tt_destroy(tt_ctx *ctx);
+
+/* Stream for all later device work of this context (a hipStream_t; NULL is
+ * the default stream). */
+int tt_set_stream(tt_ctx *ctx, void *hip_stream);
+
+/* Select TT_MAP_FP32 or TT_MAP_BF16 for tt_project / tt_adjoint. */
+int tt_set_map_precision(tt_ctx *ctx, int precision);
+
+/* Number of real even-order SH coefficients up to ell_max (or TT_EINVAL). */
+int tt_num_coeffs(int ell_max);
+
+/* Sizes of this context: out6 = {nx*ny*nz*C, n_proj*nj*nk*n_seg, C,
+ * unique segments, projections per forward batch, device work bytes}. */
+int tt_sizes(const tt_ctx *ctx, int64_t *out6);
+
+/* Copy B_{sc,i} (Eq. projection_matrix) to the host: B[n_proj][n_seg][C]. */
+int tt_basis_matrix(const tt_ctx *ctx, double *B_host);
+
+/* Host-only: B_{sc,i} for a geometry without creating a context (no device
+ * work).  B_host[n_proj][n_seg][C]. */
+int tt_geometry_basis(const tt_geometry *geom, double *B_host);
+
+/* Host-side evaluation of the real even-order spherical harmonics (section
+ * 3.2) at n directions dirs[n][3] (need not be unit length):
+ * out[n][C].  No device work. */
+int tt_sh_eval(int ell_max, int64_t n, const double *dirs, double *out);
+
+/* Forward model (Eq. forward_model): I_dev = A c_dev.  Layouts as above.
+ * Overwrites I_dev. */
+int tt_project(tt_ctx *ctx, const float *c_dev, float *I_dev);
+
+/* Adjoint: g_dev = A^T y_dev + beta * c_dev (c_dev may be NULL when
+ * beta == 0).  y_dev has the data layout, g_dev and c_dev the coefficient
+ * layout.  Overwrites g_dev. */
+int tt_adjoint(tt_ctx *ctx, const float *y_dev, float *g_dev, float beta, const float *c_dev);
+
+/* Squared loss with L2 regularisation (Eqs. opt_prob_general_form, residual):
+ *   r = A c - I_data,  L = sum w r^2 + mu sum c^2,  grad = 2 A^T (w r) + 2 mu c.
+ * w_dev may be NULL (all ones).  loss_dev receives L as one float64 on the
+ * device; resid_dev (data layout) may be NULL.  Overwrites grad_dev. */
+int tt_loss_grad(tt_ctx *ctx, const float *c_dev, const float *data_dev, const float *w_dev,
+                 double mu, double *loss_dev, float *grad_dev, float *resid_dev);
+
+/* ------------------------------------------------------------------------ */
+/* L-BFGS (section 3.5 "Optimization") on the loss above, with history m,    */
+/* initial matrix gamma I (gamma = s^T y / y^T y of the newest pair), and    */
+/* the exact line search of the quadratic loss                               */
+/*   alpha = -g^T d / (2 (||A d||_w^2 + mu ||d||^2)).                        */
+/* Pairs with s^T y <= 1e-12 ||s|| ||y|| are skipped.  All vectors stay on   */
+/* the device in float32; dot products, curvature pairs and loss reductions  */
+/* are float64.  The direction is formed from a float64 Gram matrix of the   */
+/* history (same result as the two-loop recursion), so one iteration makes   */
+/* two streaming passes over the history.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct tt_lbfgs tt_lbfgs;
+
+/* Allocate the solver state and its device history ((2m + 5) coefficient
+ * vectors and two data vectors).  The data, weight and coefficient buffers
+ * passed to tt_lbfgs_init must stay valid while the solver is used. */
+int tt_lbfgs_create(tt_ctx *ctx, int m, tt_lbfgs **out);
+void tt_lbfgs_destroy(tt_lbfgs *st);
+
+/* Start from c_dev (read and updated in place): computes r, L and grad.
+ * w_dev may be NULL.  Asynchronous. */
+int tt_lbfgs_init(tt_lbfgs *st, float *c_dev, const float *data_dev, const float *w_dev,
+                  double mu);
+
+/* One iteration (direction, forward of d, line search, update, adjoint,
+ * history update).  Asynchronous: no host synchronisation. */
+int tt_lbfgs_step(tt_lbfgs *st);
+
+/* Synchronise and read the state: out4 = {loss, ||r||_2, ||I||_2,
+ * accepted pairs}.  out4 may hold 4 doubles. */
+int tt_lbfgs_query(tt_lbfgs *st, double *out4);
+
+/* Run up to max_iter iterations, stopping once ||r|| / ||I|| <= rel_tol
+ * (checked before each iteration, one host sync per iteration).  hist (host,
+ * may be NULL) receives 2 doubles per iteration: loss and ||r||/||I||.
+ * *iters_out gets the number of iterations done. */
+int tt_lbfgs_run(tt_lbfgs *st, int max_iter, double rel_tol, double *hist, int *iters_out);
+
+/* ------------------------------------------------------------------------ */
+/* Optional kernel timing: when enabled, every kernel launch of the context  */
+/* is bracketed by HIP events on the context's stream, per kernel class.     */
+/* ------------------------------------------------------------------------ */
+enum {
+    TT_K_MAP = 0,         /* coefficient-to-segment map (MFMA), forward */
+    TT_K_MARCH = 1,       /* ray march, forward */
+    TT_K_FOLD = 2,        /* antipodal fold of the adjoint input */
+    TT_K_BACKPROJECT = 3, /* voxel-driven backprojection + MFMA map, adjoint */
+    TT_K_RESIDUAL = 4,    /* residual, loss partials and fold */
+    TT_K_VECTOR = 5,      /* L-BFGS streaming vector passes and reductions */
+    TT_K_PLAN = 6,        /* L-BFGS float64 planner kernels */
+    TT_K_COUNT = 7
+};
+int tt_timing_enable(tt_ctx *ctx, int on);
+/* Synchronise, then ms_total[k] = summed duration and launches[k] = number of
+ * launches of class k since the last read or enable; resets the counters. */
+int tt_timing_read(tt_ctx *ctx, double *ms_total, int64_t *launches);
+
+/* Last error message on this thread (never NULL). */
+const char *tt_last_error(void);
+const char *tt_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_H */

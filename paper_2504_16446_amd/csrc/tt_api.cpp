@@ -1,0 +1,634 @@
+// C ABI of the tensor-tomography hot path (see include/tt.h).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tt_internal.h"
+#include "tt_lbfgs.h"
+
+using namespace tt;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define TT_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(TT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct tt_ctx {
+    Geometry g;
+    Dims d;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = TT_MAP_FP32;
+    std::vector<ProjFrame> frames;
+    std::vector<double> B;  // [S][nseg][C] float64
+    ProjFrame *d_frames = nullptr;
+    float *d_Bu = nullptr;      // [bu_rows][Cp]: row s*Up + u, zero padded
+    uint16_t *d_Bu16 = nullptr; // bf16 copy (same layout)
+    int pb = 1;                 // projections per forward batch
+    long long vol_pad = 0;
+    float *d_M = nullptr;       // [pb][vol_pad][Up]
+    float *d_yf = nullptr;      // [S][nj][nk][Up]
+    double *d_part = nullptr;   // reduction partials
+    int n_part = 0;
+    float *d_scratch = nullptr; // data-sized scratch for tt_loss_grad without resid
+    size_t work_bytes = 0;
+    bool timing = false;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+};
+
+namespace {
+
+// Brackets the launches of one kernel class with events when timing is on.
+struct KTimer {
+    tt_ctx *c;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(tt_ctx *ctx, int k) : c(ctx), kind(k)
+    {
+        if (c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            hipEventRecord(a, c->stream);
+    }
+    ~KTimer()
+    {
+        if (b) {
+            hipEventRecord(b, c->stream);
+            c->marks.push_back({kind, a, b});
+        }
+    }
+};
+
+}  // namespace
+
+struct tt_lbfgs {
+    tt_ctx *ctx = nullptr;
+    int m = 0;
+    std::vector<float *> s, y;  // m + 1 slots each
+    float *g[2] = {nullptr, nullptr};
+    float *d = nullptr;
+    float *r = nullptr, *q = nullptr;
+    double *st = nullptr;
+    int *ist = nullptr;
+    double *part = nullptr;
+    int gcur = 0;
+    float *c = nullptr;
+    const float *data = nullptr, *w = nullptr;
+    double mu = 0.0;
+    bool inited = false;
+};
+
+static uint16_t to_bf16(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+static long long n_coef(const tt_ctx *c) { return (long long)c->d.nx * c->d.ny * c->d.nz * c->d.C; }
+static long long n_data(const tt_ctx *c) { return (long long)c->d.S * c->d.nj * c->d.nk * c->d.nseg; }
+
+extern "C" {
+
+const char *tt_last_error(void) { return g_last_error.c_str(); }
+
+const char *tt_error_string(int code)
+{
+    switch (code) {
+    case TT_OK: return "ok";
+    case TT_EINVAL: return "invalid argument";
+    case TT_ESHAPE: return "inconsistent shape";
+    case TT_ENOMEM: return "out of memory";
+    case TT_EHIP: return "HIP runtime error";
+    case TT_ENONFINITE: return "non-finite value";
+    case TT_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+    }
+}
+
+int tt_num_coeffs(int ell_max)
+{
+    if (ell_max < 0 || ell_max % 2) return fail(TT_EINVAL, "ell_max must be even and >= 0");
+    return num_coeffs(ell_max);
+}
+
+int tt_sh_eval(int ell_max, int64_t n, const double *dirs, double *out)
+{
+    if (ell_max < 0 || ell_max % 2 || ell_max > 16) return fail(TT_EINVAL, "ell_max must be even, 0..16");
+    if (n < 0 || (n > 0 && (!dirs || !out))) return fail(TT_EINVAL, "null pointer");
+    const int C = num_coeffs(ell_max);
+    for (int64_t t = 0; t < n; ++t) {
+        const double *v = dirs + 3 * t;
+        if (!(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > 0.0)) return fail(TT_EINVAL, "zero direction");
+        sh_eval_one(ell_max, v, out + C * t);
+    }
+    return TT_OK;
+}
+
+static bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+static int read_geometry(const tt_geometry *geom, Geometry &g)
+{
+    if (!geom) return fail(TT_EINVAL, "geometry is null");
+    const tt_geometry &G = *geom;
+    if (G.nx < 1 || G.ny < 1 || G.nz < 1 || G.nj < 1 || G.nk < 1 || G.n_proj < 1)
+        return fail(TT_ESHAPE, "volume, detector and projection counts must be >= 1");
+    if ((long long)G.nx * G.ny * G.nz > (1LL << 31) - 1) return fail(TT_EUNSUPPORTED, "volume above 2^31 voxels");
+    if (G.ell_max < 0 || G.ell_max % 2) return fail(TT_EINVAL, "ell_max must be even and >= 0");
+    if (G.ell_max > 16) return fail(TT_EUNSUPPORTED, "ell_max above 16");
+    if (G.n_seg < 1 || G.n_seg > 64) return fail(TT_EINVAL, "n_seg must be 1..64");
+    if (G.n_sub < 1) return fail(TT_EINVAL, "n_sub must be >= 1");
+    if (!(G.step > 0.0) || !std::isfinite(G.step)) return fail(TT_EINVAL, "step must be > 0");
+    if (!(G.seg_span > 0.0) || !std::isfinite(G.seg_span)) return fail(TT_EINVAL, "seg_span must be > 0");
+    if (G.map_precision != TT_MAP_FP32 && G.map_precision != TT_MAP_BF16)
+        return fail(TT_EINVAL, "map_precision must be TT_MAP_FP32 or TT_MAP_BF16");
+    if (!G.inner_angle || !G.outer_angle) return fail(TT_EINVAL, "angle arrays are null");
+    const double *vecs[7] = {G.p, G.j, G.k, G.q0, G.q90, G.alpha_axis, G.beta_axis};
+    for (auto v : vecs) {
+        if (!finite3(v) || !(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > 0.0))
+            return fail(TT_EINVAL, "geometry vectors must be finite and nonzero");
+    }
+    // the raster directions and the beam must form an orthonormal frame
+    auto dot = [](const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    if (std::fabs(dot(G.p, G.j)) > 1e-9 || std::fabs(dot(G.p, G.k)) > 1e-9 || std::fabs(dot(G.j, G.k)) > 1e-9 ||
+        std::fabs(dot(G.p, G.p) - 1) > 1e-9 || std::fabs(dot(G.j, G.j) - 1) > 1e-9 || std::fabs(dot(G.k, G.k) - 1) > 1e-9)
+        return fail(TT_EINVAL, "p, j, k must be orthonormal");
+    g.nx = G.nx; g.ny = G.ny; g.nz = G.nz; g.ell_max = G.ell_max; g.n_proj = G.n_proj;
+    g.nj = G.nj; g.nk = G.nk; g.n_seg = G.n_seg; g.n_sub = G.n_sub;
+    g.step = G.step; g.seg_span = G.seg_span;
+    g.inner.assign(G.inner_angle, G.inner_angle + G.n_proj);
+    g.outer.assign(G.outer_angle, G.outer_angle + G.n_proj);
+    g.joff.assign(G.n_proj, 0.0);
+    g.koff.assign(G.n_proj, 0.0);
+    if (G.j_offset) g.joff.assign(G.j_offset, G.j_offset + G.n_proj);
+    if (G.k_offset) g.koff.assign(G.k_offset, G.k_offset + G.n_proj);
+    for (int s = 0; s < G.n_proj; ++s)
+        if (!std::isfinite(g.inner[s]) || !std::isfinite(g.outer[s]) || !std::isfinite(g.joff[s]) ||
+            !std::isfinite(g.koff[s]))
+            return fail(TT_EINVAL, "non-finite angle or offset");
+    std::memcpy(g.p, G.p, sizeof g.p); std::memcpy(g.j, G.j, sizeof g.j); std::memcpy(g.k, G.k, sizeof g.k);
+    std::memcpy(g.q0, G.q0, sizeof g.q0); std::memcpy(g.q90, G.q90, sizeof g.q90);
+    std::memcpy(g.alpha_axis, G.alpha_axis, sizeof g.alpha_axis);
+    std::memcpy(g.beta_axis, G.beta_axis, sizeof g.beta_axis);
+    return TT_OK;
+}
+
+int tt_geometry_basis(const tt_geometry *geom, double *B_host)
+{
+    if (!B_host) return fail(TT_EINVAL, "B_host is null");
+    Geometry g;
+    int rc = read_geometry(geom, g);
+    if (rc) return rc;
+    std::vector<ProjFrame> frames;
+    std::vector<double> B;
+    build_frames(g, frames, B);
+    std::memcpy(B_host, B.data(), B.size() * sizeof(double));
+    return TT_OK;
+}
+
+int tt_create(const tt_geometry *geom, tt_ctx **out)
+{
+    if (!out) return fail(TT_EINVAL, "out is null");
+    *out = nullptr;
+    tt_ctx *c = new (std::nothrow) tt_ctx();
+    if (!c) return fail(TT_ENOMEM, "host allocation failed");
+    Geometry &g = c->g;
+    int rc0 = read_geometry(geom, g);
+    if (rc0) {
+        delete c;
+        return rc0;
+    }
+    c->precision = geom->map_precision;
+
+    build_frames(g, c->frames, c->B);
+
+    Dims &d = c->d;
+    d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+    d.C = num_coeffs(g.ell_max);
+    d.Cp = round_up(d.C, 16);
+    d.S = g.n_proj; d.nj = g.nj; d.nk = g.nk; d.nseg = g.n_seg;
+    d.step = (float)g.step;
+    // Even orders: Y(-q) = Y(q), and with segments over the full circle segment
+    // c + n_seg/2 probes exactly the antipodes of segment c.
+    const bool antipodal = std::fabs(g.seg_span - 2.0 * M_PI) < 1e-12 && g.n_seg % 2 == 0;
+    d.U = antipodal ? g.n_seg / 2 : g.n_seg;
+    if (d.U > 16) {
+        delete c;
+        return fail(TT_EUNSUPPORTED, "more than 16 distinct segments");
+    }
+    d.Up = d.U <= 4 ? 4 : (d.U <= 8 ? 8 : 16);
+
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(TT_EHIP, "hipGetDevice failed");
+    }
+    const int S = d.S;
+    const int bu_rows = round_up(S * d.Up, 256) + 256;
+    std::vector<float> bu((size_t)bu_rows * d.Cp, 0.0f);
+    std::vector<uint16_t> bu16((size_t)bu_rows * d.Cp, 0);
+    for (int s = 0; s < S; ++s)
+        for (int u = 0; u < d.U; ++u)
+            for (int i = 0; i < d.C; ++i) {
+                float v = (float)c->B[((size_t)s * d.nseg + u) * d.C + i];
+                bu[((size_t)s * d.Up + u) * d.Cp + i] = v;
+                bu16[((size_t)s * d.Up + u) * d.Cp + i] = to_bf16(v);
+            }
+    c->vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
+    const size_t per_proj = (size_t)c->vol_pad * d.Up * sizeof(float);
+    size_t budget = (size_t)1 << 30;
+    if (const char *e = std::getenv("TT_FORWARD_BATCH_BYTES")) budget = (size_t)std::strtoull(e, nullptr, 10);
+    c->pb = (int)std::max<size_t>(1, std::min<size_t>((size_t)S, budget / per_proj));
+    c->n_part = 1024 + std::max(4096, backproject_blocks(d));
+    const size_t yf_bytes = (size_t)S * d.nj * d.nk * d.Up * sizeof(float);
+
+    auto cleanup = [&](int code, const std::string &msg) {
+        tt_destroy(c);
+        return fail(code, msg);
+    };
+    if (hipMalloc(&c->d_frames, sizeof(ProjFrame) * S) != hipSuccess ||
+        hipMalloc(&c->d_Bu, bu.size() * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_Bu16, bu16.size() * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&c->d_M, per_proj * c->pb) != hipSuccess || hipMalloc(&c->d_yf, yf_bytes) != hipSuccess ||
+        hipMalloc(&c->d_part, sizeof(double) * c->n_part) != hipSuccess)
+        return cleanup(TT_ENOMEM, "device allocation failed");
+    c->work_bytes = per_proj * c->pb + yf_bytes + sizeof(double) * c->n_part + bu.size() * 6;
+    if (hipMemcpy(c->d_frames, c->frames.data(), sizeof(ProjFrame) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_Bu, bu.data(), bu.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_Bu16, bu16.data(), bu16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(c->d_M, 0, per_proj * c->pb) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return cleanup(TT_EHIP, "device upload failed");
+    *out = c;
+    return TT_OK;
+}
+
+void tt_destroy(tt_ctx *c)
+{
+    if (!c) return;
+    tt_timing_enable(c, 0);
+    hipFree(c->d_frames);
+    hipFree(c->d_Bu);
+    hipFree(c->d_Bu16);
+    hipFree(c->d_M);
+    hipFree(c->d_yf);
+    hipFree(c->d_part);
+    hipFree(c->d_scratch);
+    delete c;
+}
+
+int tt_set_stream(tt_ctx *c, void *stream)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    c->stream = (hipStream_t)stream;
+    return TT_OK;
+}
+
+int tt_set_map_precision(tt_ctx *c, int precision)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    if (precision != TT_MAP_FP32 && precision != TT_MAP_BF16) return fail(TT_EINVAL, "bad precision");
+    c->precision = precision;
+    return TT_OK;
+}
+
+int tt_timing_enable(tt_ctx *c, int on)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    for (auto &mk : c->marks) {
+        hipEventDestroy(mk.a);
+        hipEventDestroy(mk.b);
+    }
+    c->marks.clear();
+    c->timing = on != 0;
+    return TT_OK;
+}
+
+int tt_timing_read(tt_ctx *c, double *ms_total, int64_t *launches)
+{
+    if (!c || !ms_total || !launches) return fail(TT_EINVAL, "null pointer");
+    TT_HIP(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < TT_K_COUNT; ++k) {
+        ms_total[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &mk : c->marks) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
+            ms_total[mk.kind] += ms;
+            launches[mk.kind] += 1;
+        }
+        hipEventDestroy(mk.a);
+        hipEventDestroy(mk.b);
+    }
+    c->marks.clear();
+    return TT_OK;
+}
+
+int tt_sizes(const tt_ctx *c, int64_t *out6)
+{
+    if (!c || !out6) return fail(TT_EINVAL, "null pointer");
+    out6[0] = n_coef(c);
+    out6[1] = n_data(c);
+    out6[2] = c->d.C;
+    out6[3] = c->d.U;
+    out6[4] = c->pb;
+    out6[5] = (int64_t)c->work_bytes;
+    return TT_OK;
+}
+
+int tt_basis_matrix(const tt_ctx *c, double *B_host)
+{
+    if (!c || !B_host) return fail(TT_EINVAL, "null pointer");
+    std::memcpy(B_host, c->B.data(), c->B.size() * sizeof(double));
+    return TT_OK;
+}
+
+static int project_impl(tt_ctx *c, const float *cin, float *I)
+{
+    for (int s0 = 0; s0 < c->d.S; s0 += c->pb) {
+        const int np = std::min(c->pb, c->d.S - s0);
+        hipError_t e;
+        {
+            KTimer t(c, TT_K_MAP);
+            e = c->precision == TT_MAP_BF16 ? launch_map_bf16(c->d, cin, c->d_Bu16, s0, np, c->d_M, c->stream)
+                                            : launch_map_fp32(c->d, cin, c->d_Bu, s0, np, c->d_M, c->stream);
+        }
+        if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
+                                         std::string("map: ") + hipGetErrorString(e));
+        {
+            KTimer t(c, TT_K_MARCH);
+            e = launch_march(c->d, c->d_frames, c->d_M, s0, np, I, c->stream);
+        }
+        if (e != hipSuccess) return fail(TT_EHIP, std::string("march: ") + hipGetErrorString(e));
+    }
+    return TT_OK;
+}
+
+int tt_project(tt_ctx *c, const float *cin, float *I)
+{
+    if (!c || !cin || !I) return fail(TT_EINVAL, "null pointer");
+    return project_impl(c, cin, I);
+}
+
+static int backproject_impl(tt_ctx *c, float *g, float beta, const float *cin, double *partials)
+{
+    hipError_t e;
+    {
+        KTimer t(c, TT_K_BACKPROJECT);
+        e = launch_backproject(c->d, c->d_frames, c->d_yf, c->d_Bu, c->d_Bu16, c->precision == TT_MAP_BF16, g, beta,
+                               cin, partials, c->stream);
+    }
+    if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
+                                     std::string("backproject: ") + hipGetErrorString(e));
+    return TT_OK;
+}
+
+int tt_adjoint(tt_ctx *c, const float *y, float *g, float beta, const float *cin)
+{
+    if (!c || !y || !g) return fail(TT_EINVAL, "null pointer");
+    if (beta != 0.0f && !cin) return fail(TT_EINVAL, "beta != 0 needs c");
+    {
+        KTimer t(c, TT_K_FOLD);
+        TT_HIP(launch_fold(c->d, y, c->d.step, c->d_yf, c->stream));
+    }
+    return backproject_impl(c, g, beta, beta != 0.0f ? cin : nullptr, nullptr);
+}
+
+int tt_loss_grad(tt_ctx *c, const float *cin, const float *data, const float *w, double mu, double *loss,
+                 float *grad, float *resid)
+{
+    if (!c || !cin || !data || !loss || !grad) return fail(TT_EINVAL, "null pointer");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(TT_EINVAL, "mu must be finite and >= 0");
+    float *r = resid;
+    if (!r) {
+        if (!c->d_scratch && hipMalloc(&c->d_scratch, sizeof(float) * n_data(c)) != hipSuccess)
+            return fail(TT_ENOMEM, "scratch allocation failed");
+        r = c->d_scratch;
+    }
+    int rc = project_impl(c, cin, r);
+    if (rc) return rc;
+    const int nb = 1024;
+    {
+        KTimer t(c, TT_K_RESIDUAL);
+        TT_HIP(launch_residual_fold(c->d, r, data, w, r, c->d_yf, c->d_part, nb, c->stream));
+        TT_HIP(launch_sum_partials(c->d_part, nb, loss, 1.0, 0, c->stream));
+    }
+    double *p2 = c->d_part + nb;
+    rc = backproject_impl(c, grad, (float)(2.0 * mu), cin, p2);
+    if (rc) return rc;
+    TT_HIP(launch_sum_partials(p2, backproject_blocks(c->d), loss, mu, 1, c->stream));
+    return TT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// L-BFGS
+// ---------------------------------------------------------------------------
+void tt_lbfgs_destroy(tt_lbfgs *st)
+{
+    if (!st) return;
+    for (float *p : st->s) hipFree(p);
+    for (float *p : st->y) hipFree(p);
+    hipFree(st->g[0]);
+    hipFree(st->g[1]);
+    hipFree(st->d);
+    hipFree(st->r);
+    hipFree(st->q);
+    hipFree(st->st);
+    hipFree(st->ist);
+    hipFree(st->part);
+    delete st;
+}
+
+int tt_lbfgs_create(tt_ctx *c, int m, tt_lbfgs **out)
+{
+    if (!out) return fail(TT_EINVAL, "out is null");
+    *out = nullptr;
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    if (m < 1 || m > kMaxM) return fail(TT_EUNSUPPORTED, "history m must be 1.." + std::to_string(kMaxM));
+    tt_lbfgs *st = new (std::nothrow) tt_lbfgs();
+    if (!st) return fail(TT_ENOMEM, "host allocation failed");
+    st->ctx = c;
+    st->m = m;
+    const size_t vb = sizeof(float) * n_coef(c), db = sizeof(float) * n_data(c);
+    st->s.assign(m + 1, nullptr);
+    st->y.assign(m + 1, nullptr);
+    bool ok = true;
+    for (int i = 0; i <= m; ++i) {
+        ok &= hipMalloc(&st->s[i], vb) == hipSuccess && hipMemset(st->s[i], 0, vb) == hipSuccess;
+        ok &= hipMalloc(&st->y[i], vb) == hipSuccess && hipMemset(st->y[i], 0, vb) == hipSuccess;
+    }
+    ok &= hipMalloc(&st->g[0], vb) == hipSuccess && hipMalloc(&st->g[1], vb) == hipSuccess;
+    ok &= hipMalloc(&st->d, vb) == hipSuccess;
+    ok &= hipMalloc(&st->r, db) == hipSuccess && hipMalloc(&st->q, db) == hipSuccess;
+    ok &= hipMalloc(&st->st, sizeof(double) * kStateDoubles) == hipSuccess;
+    ok &= hipMalloc(&st->ist, sizeof(int) * kStateInts) == hipSuccess;
+    ok &= hipMalloc(&st->part, sizeof(double) * (kMaxBasis + 1) * lbfgs_blocks()) == hipSuccess;
+    if (!ok || hipDeviceSynchronize() != hipSuccess) {
+        tt_lbfgs_destroy(st);
+        return fail(TT_ENOMEM, "L-BFGS device allocation failed");
+    }
+    *out = st;
+    return TT_OK;
+}
+
+int tt_lbfgs_init(tt_lbfgs *st, float *cin, const float *data, const float *w, double mu)
+{
+    if (!st || !cin || !data) return fail(TT_EINVAL, "null pointer");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(TT_EINVAL, "mu must be finite and >= 0");
+    tt_ctx *c = st->ctx;
+    hipStream_t s = c->stream;
+    st->c = cin;
+    st->data = data;
+    st->w = w;
+    st->mu = mu;
+    st->gcur = 0;
+    const int m = st->m, ns = m + 1, gi = 2 * ns;
+    const long long n = n_coef(c), nd = n_data(c);
+    // host-prepared initial state: empty ring, gamma = 1
+    std::vector<double> h(kStateDoubles, 0.0);
+    std::vector<int> hi(kStateInts, 0);
+    h[kGamma] = 1.0;
+    hi[kMask2] = 1;  // first list entry (the gradient) for the initial dot product
+    TT_HIP(hipMemcpyAsync(st->st, h.data(), sizeof(double) * kStateDoubles, hipMemcpyHostToDevice, s));
+    TT_HIP(hipMemcpyAsync(st->ist, hi.data(), sizeof(int) * kStateInts, hipMemcpyHostToDevice, s));
+    int rc = project_impl(c, cin, st->r);
+    if (rc) return rc;
+    TT_HIP(launch_residual_fold(c->d, st->r, data, w, st->r, c->d_yf, c->d_part, 1024, s));
+    TT_HIP(launch_sum_partials(c->d_part, 1024, st->st + kLossR, 1.0, 0, s));
+    TT_HIP(lbfgs_wnorm2(st->r, nullptr, nd, st->part, st->st + kRR, s));
+    TT_HIP(lbfgs_wnorm2(data, nullptr, nd, st->part, st->st + kDataNorm2, s));
+    double *p2 = c->d_part + 1024;
+    rc = backproject_impl(c, st->g[0], (float)(2.0 * mu), cin, p2);
+    if (rc) return rc;
+    TT_HIP(launch_sum_partials(p2, backproject_blocks(c->d), st->st + kCC, 1.0, 0, s));
+    const float *gl[1] = {st->g[0]};
+    TT_HIP(lbfgs_multidot(st->g[0], gl, 1, st->ist + kMask2, n, st->part, st->st + kDotsG, s));
+    // G[g][g] = g . g  (copied on the device)
+    TT_HIP(hipMemcpyAsync(st->st + kGram + gi * kMaxBasis + gi, st->st + kDotsG, sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+    st->inited = true;
+    return TT_OK;
+}
+
+int tt_lbfgs_step(tt_lbfgs *st)
+{
+    if (!st || !st->inited) return fail(TT_EINVAL, "solver not initialised");
+    tt_ctx *c = st->ctx;
+    hipStream_t s = c->stream;
+    const int m = st->m, ns = m + 1;
+    const long long n = n_coef(c);
+    float *gold = st->g[st->gcur], *gnew = st->g[1 - st->gcur];
+    std::vector<const float *> basis(2 * ns + 2);
+    for (int i = 0; i < ns; ++i) {
+        basis[i] = st->s[i];
+        basis[ns + i] = st->y[i];
+    }
+    basis[2 * ns] = gold;
+    basis[2 * ns + 1] = gnew;
+    {
+        KTimer t(c, TT_K_PLAN);
+        TT_HIP(lbfgs_plan_direction(st->st, st->ist, m, s));
+    }
+    {
+        KTimer t(c, TT_K_VECTOR);
+        TT_HIP(lbfgs_combine(basis.data(), 2 * ns + 1, st->st + kCoef, st->ist + kMask, n, st->d, st->part,
+                             st->st + kDotsD, s));
+    }
+    int rc = project_impl(c, st->d, st->q);
+    if (rc) return rc;
+    {
+        KTimer t(c, TT_K_VECTOR);
+        TT_HIP(lbfgs_wnorm2(st->q, st->w, n_data(c), st->part, st->st + kQQ, s));
+    }
+    {
+        KTimer t(c, TT_K_PLAN);
+        TT_HIP(lbfgs_plan_alpha(st->st, st->ist, m, st->mu, s));
+    }
+    {
+        KTimer t(c, TT_K_VECTOR);
+        TT_HIP(lbfgs_update_c(st->c, st->d, basis.data(), ns, st->st, st->ist, n, s));
+    }
+    {
+        KTimer t(c, TT_K_RESIDUAL);
+        TT_HIP(lbfgs_resid_update(c->d, st->r, st->q, st->w, st->st, c->d_yf, st->part, st->st + kLossR, s));
+    }
+    double *p2 = c->d_part + 1024;
+    rc = backproject_impl(c, gnew, (float)(2.0 * st->mu), st->c, p2);
+    if (rc) return rc;
+    {
+        KTimer t(c, TT_K_VECTOR);
+        TT_HIP(launch_sum_partials(p2, backproject_blocks(c->d), st->st + kCC, 1.0, 0, s));
+        TT_HIP(lbfgs_multidot(gnew, basis.data(), 2 * ns + 2, st->ist + kMask2, n, st->part, st->st + kDotsG, s));
+    }
+    {
+        KTimer t(c, TT_K_PLAN);
+        TT_HIP(lbfgs_plan_update(st->st, st->ist, m, st->mu, s));
+    }
+    {
+        KTimer t(c, TT_K_VECTOR);
+        TT_HIP(lbfgs_make_y(basis.data() + ns, ns, st->ist, gnew, gold, n, s));
+    }
+    st->gcur = 1 - st->gcur;
+    return TT_OK;
+}
+
+int tt_lbfgs_query(tt_lbfgs *st, double *out4)
+{
+    if (!st || !out4) return fail(TT_EINVAL, "null pointer");
+    if (!st->inited) return fail(TT_EINVAL, "solver not initialised");
+    TT_HIP(hipStreamSynchronize(st->ctx->stream));
+    double h[kStateDoubles];
+    int hi[kStateInts];
+    TT_HIP(hipMemcpy(h, st->st, sizeof h, hipMemcpyDeviceToHost));
+    TT_HIP(hipMemcpy(hi, st->ist, sizeof hi, hipMemcpyDeviceToHost));
+    out4[0] = h[kLossR] + st->mu * h[kCC];
+    out4[1] = std::sqrt(h[kRR]);
+    out4[2] = std::sqrt(h[kDataNorm2]);
+    out4[3] = hi[kAccepted];
+    if (!std::isfinite(out4[0]) || !std::isfinite(out4[1])) return fail(TT_ENONFINITE, "non-finite loss or residual");
+    return TT_OK;
+}
+
+int tt_lbfgs_run(tt_lbfgs *st, int max_iter, double rel_tol, double *hist, int *iters_out)
+{
+    if (!st) return fail(TT_EINVAL, "null pointer");
+    if (max_iter < 0) return fail(TT_EINVAL, "max_iter must be >= 0");
+    int it = 0;
+    double q[4];
+    int rc = tt_lbfgs_query(st, q);
+    for (; rc == TT_OK && it < max_iter; ++it) {
+        if (q[1] <= rel_tol * q[2]) break;
+        rc = tt_lbfgs_step(st);
+        if (rc == TT_OK) rc = tt_lbfgs_query(st, q);
+        if (rc == TT_OK && hist) {
+            hist[2 * it] = q[0];
+            hist[2 * it + 1] = q[1] / q[2];
+        }
+    }
+    if (iters_out) *iters_out = it;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,24 @@
+// Device-only helpers shared by the kernel sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tt {
+
+// Block-wide float64 sum; the result is valid in thread 0.  ws must hold
+// blockDim.x / 64 doubles of shared memory.  Contains barriers: every thread
+// of the block must call it.
+__device__ __forceinline__ double block_sum(double v, double *ws)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) ws[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += ws[i];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace tt

@@ -1,0 +1,140 @@
+// Host-side float64 precompute: spherical harmonics, goniometer rotations,
+// ray frames and segment-averaged basis constants.
+//
+// Spherical harmonics (paper section 3.2): real, orthonormal, even orders.
+// Evaluated with the fully normalised associated-Legendre recurrence
+//   Pbar_mm     = Pbar_{m-1,m-1} s sqrt((2m+1)/(2m)),     Pbar_00 = 1/sqrt(4 pi)
+//   Pbar_{m+1,m} = x sqrt(2m+3) Pbar_mm
+//   Pbar_lm     = a_lm (x Pbar_{l-1,m} - Pbar_{l-2,m} / a_{l-1,m}),
+//   a_lm        = sqrt((4 l^2 - 1) / (l^2 - m^2)),
+// and cos(m phi), sin(m phi) by the Chebyshev recurrence from the direction's
+// x/s and y/s, so no angle is ever formed.  Y_l0 = Pbar_l0,
+// Y_lm = sqrt2 Pbar_lm cos(m phi), Y_l,-m = sqrt2 Pbar_lm sin(m phi) (m > 0),
+// without the Condon-Shortley phase; index i(l, m) = l(l-1)/2 + l + m.
+//
+// Goniometer (section 2): R_s = R_beta(beta_s) R_alpha(alpha_s), composed here
+// as unit quaternions.  Ray frame of projection s in sample coordinates:
+// e_j = R^T j, e_k = R^T k, d = R^T p (Eq. real_space_geom), origin of pixel
+// (0, 0) at -((nj-1)/2 + dj) e_j - ((nk-1)/2 + dk) e_k.
+//
+// Basis constants (Eq. projection_matrix): mean of Y_i(R_s^T q(phi)) over the
+// n_sub midpoint nodes of segment c, q(phi) = cos(phi) q0 + sin(phi) q90
+// (small-angle form of Eq. 1), segment c centred at c * span / n_seg.
+#include "tt_internal.h"
+
+#include <cmath>
+#include <vector>
+
+namespace tt {
+
+int num_coeffs(int ell_max) { return (ell_max / 2 + 1) * (ell_max + 1); }
+
+void sh_eval_one(int ell_max, const double *dir, double *out)
+{
+    const double kFourPi = 4.0 * M_PI;
+    double r = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    double x = dir[2] / r;
+    double sx = dir[0] / r, sy = dir[1] / r;
+    double s = std::sqrt(sx * sx + sy * sy);
+    double cphi = 1.0, sphi = 0.0;
+    if (s > 0.0) {
+        cphi = sx / s;
+        sphi = sy / s;
+    }
+    // Pbar[l][m] for m <= l <= ell_max (small, on the stack)
+    double P[17][17];
+    P[0][0] = 1.0 / std::sqrt(kFourPi);
+    for (int m = 1; m <= ell_max; ++m) P[m][m] = P[m - 1][m - 1] * s * std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+    for (int m = 0; m < ell_max; ++m) P[m + 1][m] = x * std::sqrt(2.0 * m + 3.0) * P[m][m];
+    for (int m = 0; m <= ell_max; ++m)
+        for (int l = m + 2; l <= ell_max; ++l) {
+            double a = std::sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+            double ap = std::sqrt((4.0 * (l - 1) * (l - 1) - 1.0) / ((double)(l - 1) * (l - 1) - (double)m * m));
+            P[l][m] = a * (x * P[l - 1][m] - P[l - 2][m] / ap);
+        }
+    double cm[17], sm[17];
+    cm[0] = 1.0;
+    sm[0] = 0.0;
+    for (int m = 1; m <= ell_max; ++m) {
+        cm[m] = cm[m - 1] * cphi - sm[m - 1] * sphi;
+        sm[m] = sm[m - 1] * cphi + cm[m - 1] * sphi;
+    }
+    const double r2 = std::sqrt(2.0);
+    int i = 0;
+    for (int l = 0; l <= ell_max; l += 2) {
+        for (int m = l; m >= 1; --m) out[i++] = r2 * P[l][m] * sm[m];
+        out[i++] = P[l][0];
+        for (int m = 1; m <= l; ++m) out[i++] = r2 * P[l][m] * cm[m];
+    }
+}
+
+namespace {
+
+struct Quat {
+    double w, x, y, z;
+};
+
+Quat axis_angle(const double *axis, double th)
+{
+    double n = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    double h = 0.5 * th, sh = std::sin(h) / n;
+    return {std::cos(h), axis[0] * sh, axis[1] * sh, axis[2] * sh};
+}
+
+Quat mul(const Quat &a, const Quat &b)
+{
+    return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z,
+            a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+            a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x,
+            a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+
+// R^T v for the rotation of unit quaternion q: rotate v by the conjugate.
+void rotate_inverse(const Quat &q, const double *v, double *out)
+{
+    // v' = v + 2 w (u x v) + 2 u x (u x v) with u = -q.xyz, w = q.w
+    double ux = -q.x, uy = -q.y, uz = -q.z;
+    double tx = 2.0 * (uy * v[2] - uz * v[1]);
+    double ty = 2.0 * (uz * v[0] - ux * v[2]);
+    double tz = 2.0 * (ux * v[1] - uy * v[0]);
+    out[0] = v[0] + q.w * tx + (uy * tz - uz * ty);
+    out[1] = v[1] + q.w * ty + (uz * tx - ux * tz);
+    out[2] = v[2] + q.w * tz + (ux * ty - uy * tx);
+}
+
+}  // namespace
+
+void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector<double> &B)
+{
+    const int S = g.n_proj, C = num_coeffs(g.ell_max);
+    frames.resize(S);
+    B.assign((size_t)S * g.n_seg * C, 0.0);
+    std::vector<double> y(C);
+    for (int s = 0; s < S; ++s) {
+        Quat q = mul(axis_angle(g.beta_axis, g.outer[s]), axis_angle(g.alpha_axis, g.inner[s]));
+        ProjFrame &f = frames[s];
+        rotate_inverse(q, g.j, f.ej);
+        rotate_inverse(q, g.k, f.ek);
+        rotate_inverse(q, g.p, f.d);
+        double cj = 0.5 * (g.nj - 1) + g.joff[s];
+        double ck = 0.5 * (g.nk - 1) + g.koff[s];
+        for (int a = 0; a < 3; ++a) f.o[a] = -cj * f.ej[a] - ck * f.ek[a];
+        f.lj = std::fabs(f.ej[0]) + std::fabs(f.ej[1]) + std::fabs(f.ej[2]);
+        f.lk = std::fabs(f.ek[0]) + std::fabs(f.ek[1]) + std::fabs(f.ek[2]);
+        for (int a = 0; a < 3; ++a) f.inv_d[a] = std::fabs(f.d[a]) > 1e-12 ? 1.0 / f.d[a] : 0.0;
+        for (int c = 0; c < g.n_seg; ++c) {
+            double *row = &B[((size_t)s * g.n_seg + c) * C];
+            for (int m = 0; m < g.n_sub; ++m) {
+                double phi = (c - 0.5 + (m + 0.5) / g.n_sub) * g.seg_span / g.n_seg;
+                double qd[3], qs[3];
+                for (int a = 0; a < 3; ++a) qd[a] = std::cos(phi) * g.q0[a] + std::sin(phi) * g.q90[a];
+                rotate_inverse(q, qd, qs);
+                sh_eval_one(g.ell_max, qs, y.data());
+                for (int i = 0; i < C; ++i) row[i] += y[i];
+            }
+            for (int i = 0; i < C; ++i) row[i] /= g.n_sub;
+        }
+    }
+}
+
+}  // namespace tt

@@ -1,0 +1,71 @@
+// Internal declarations shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tt.h"
+
+namespace tt {
+
+// Geometry copied out of tt_geometry, with offsets defaulted to zero.
+struct Geometry {
+    int nx, ny, nz, ell_max, n_proj, nj, nk, n_seg, n_sub;
+    double step, seg_span;
+    std::vector<double> inner, outer, joff, koff;
+    double p[3], j[3], k[3], q0[3], q90[3], alpha_axis[3], beta_axis[3];
+};
+
+// Ray frame of one projection, float64, in centred sample coordinates.
+// The ray through pixel (j, k) is o + j e_j + k e_k + t d.
+struct ProjFrame {
+    double o[3];
+    double ej[3], ek[3], d[3];
+    double inv_d[3];  // 1 / d_a, or 0 when the ray is parallel to plane a
+    double lj, lk;    // L1 norms of e_j and e_k (bounds of the pixel window)
+};
+
+int num_coeffs(int ell_max);
+void sh_eval_one(int ell_max, const double *dir, double *out);
+void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector<double> &B);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (tt_proj.hip, tt_vec.hip).  All asynchronous on `st`.
+// ---------------------------------------------------------------------------
+struct Dims {
+    int nx, ny, nz;     // volume
+    int C, Cp;          // coefficients, padded to a multiple of 16
+    int S, nj, nk;      // projections and detector
+    int nseg, U, Up;    // segments, unique segments, padded unique segments
+    float step;
+};
+
+// M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
+hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
+                           hipStream_t st);
+hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bu16, int s0, int np,
+                           float *M, hipStream_t st);
+// I[s0+p][j][k][c] = step * ray sums of M[p] along the rays of projection s0+p.
+hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np,
+                        float *I, hipStream_t st);
+// yf[s][j][k][u] = scale * sum_{c: c mod U = u} y[s][j][k][c] (optionally
+// y = 2 w (Ip - data) with the loss partials, see launch_residual_fold).
+hipError_t launch_fold(const Dims &d, const float *y, float scale, float *yf, hipStream_t st);
+// r = Ip - data (stored to r if non-null), yf = fold(2 w r) * step, and the
+// float64 partial sums of w r^2 per block into partials.
+hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *data, const float *w,
+                                float *r, float *yf, double *partials, int nblocks, hipStream_t st);
+// g = A^T-part(yf) + beta c, with float64 partials of sum c^2 when c != null.
+hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const float *yf,
+                              const float *Bu, const uint16_t *Bu16, int bf16, float *g, float beta,
+                              const float *c, double *partials, hipStream_t st);
+int backproject_blocks(const Dims &d);
+
+// Reductions: out[slot] = scale * sum of partials[0..n).
+hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,
+                               int accumulate, hipStream_t st);
+
+}  // namespace tt

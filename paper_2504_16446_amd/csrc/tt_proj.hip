@@ -1,0 +1,503 @@
+// Forward model and adjoint kernels for gfx950.
+//
+// Forward (Eq. forward_model, evaluated in the order the paper writes it):
+//   1. map:    M_s[v][u] = sum_i B_{s,u,i} c_{v,i}       (MFMA, one pass over c
+//              serves a batch of projections; u runs over the unique segments
+//              only -- for even orders segments c and c + n_seg/2 coincide)
+//   2. march:  I_{s,j,k,c} = step * sum_n sum_{8 corners} T(x_n - x_v) M_s[v][c mod U]
+//              (one thread per ray, float64 sample positions, float32 sums)
+// Adjoint (transpose, voxel-driven so no atomics are needed):
+//   yf[s][j][k][u] = step * sum_{c mod U = u} y[s][j][k][c]
+//   g_v = sum_s B_s^T Q_s(v),  Q_s(v)[u] = sum_{(j,k,n)} T(x_n - x_v) yf[s][j][k][u]
+//   Each thread owns one voxel and enumerates the rays within the L1 radius of
+//   its detector position and the samples of each ray inside its tent support;
+//   each wave then contracts its 64 voxels' Q_s with B_s on MFMA, accumulating
+//   g in registers over all projections.
+#include "tt_device.h"
+#include "tt_internal.h"
+
+namespace tt {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// MFMA 16x16x4 fp32 operand layout (one wave):
+//   A[16][4]: lane l supplies A[l % 16][l / 16]
+//   B[4][16]: lane l supplies B[l / 16][l % 16]
+//   D[16][16]: lane l holds D[4 (l / 16) + r][l % 16], r = 0..3
+__device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ long long pad_index(int v, int ny, int nz)
+{
+    int iz = v % nz;
+    int t = v / nz;
+    int iy = t % ny;
+    int ix = t / ny;
+    return ((long long)(ix + 1) * (ny + 2) + (iy + 1)) * (nz + 2) + (iz + 1);
+}
+
+// ---------------------------------------------------------------------------
+// map (fp32 MFMA).  Block = 64 voxels x 256 rows (row = p * UP + u).
+// Each wave owns one 16-voxel column tile and loops over 16 row tiles.
+// ---------------------------------------------------------------------------
+constexpr int kCtStride = 80;  // padded voxel stride of the transposed c tile in LDS
+
+template <int UP>
+__global__ __launch_bounds__(256) void k_map_fp32(const float *__restrict__ c, const float *__restrict__ Bu,
+                                                  int V, int C, int Cp, int ny, int nz, int s0, int np,
+                                                  long long vol_pad, float *__restrict__ M)
+{
+    extern __shared__ float cT[];  // [Cp][kCtStride]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int v0 = blockIdx.x * 64;
+    const int nv = min(64, V - v0);
+    const float *cb = c + (long long)v0 * C;
+    for (int e = tid; e < 64 * Cp; e += 256) {
+        int k = e / 64, v = e % 64;
+        cT[k * kCtStride + v] = 0.0f;
+    }
+    __syncthreads();
+    for (int e = tid; e < nv * C; e += 256) {
+        int v = e / C, k = e - v * C;
+        cT[k * kCtStride + v] = cb[e];
+    }
+    __syncthreads();
+
+    const int col = wave * 16 + (lane & 15);  // voxel within block
+    const int kq = lane >> 4;
+    const int v = v0 + col;
+    const long long vp = v < V ? pad_index(v, ny, nz) : 0;
+    const int row0 = blockIdx.y * 256;
+    const float *Bb = Bu + ((long long)s0 * UP + row0) * Cp;
+    for (int mt = 0; mt < 16; ++mt) {
+        const float *Ar = Bb + (long long)(mt * 16 + (lane & 15)) * Cp + kq;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < Cp / 4; ++ks) {
+            float a = Ar[ks * 4];
+            float b = cT[(ks * 4 + kq) * kCtStride + col];
+            acc = mfma16x16x4(a, b, acc);
+        }
+        const int row = row0 + mt * 16 + 4 * kq;  // first of the 4 rows held by this lane
+        const int p = row / UP, u0 = row % UP;
+        if (p < np && v < V) {
+            float *dst = M + (long long)p * vol_pad * UP + vp * UP + u0;
+            *reinterpret_cast<f4 *>(dst) = acc;
+        }
+    }
+}
+
+template <int UP>
+static hipError_t map_fp32_t(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
+                             hipStream_t st)
+{
+    const int V = d.nx * d.ny * d.nz;
+    const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
+    dim3 grid((V + 63) / 64, (np * UP + 255) / 256);
+    size_t lds = (size_t)d.Cp * kCtStride * sizeof(float);
+    hipLaunchKernelGGL(k_map_fp32<UP>, grid, dim3(256), lds, st, c, Bu, V, d.C, d.Cp, d.ny, d.nz, s0, np,
+                       vol_pad, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
+                           hipStream_t st)
+{
+    switch (d.Up) {
+    case 4: return map_fp32_t<4>(d, c, Bu, s0, np, M, st);
+    case 8: return map_fp32_t<8>(d, c, Bu, s0, np, M, st);
+    case 16: return map_fp32_t<16>(d, c, Bu, s0, np, M, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_map_bf16(const Dims &, const float *, const uint16_t *, int, int, float *, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+// ---------------------------------------------------------------------------
+// march: one thread per ray; block = 16 (j) x 16 (k) rays of one projection.
+// Positions are float64 in padded index coordinates (voxel ix sits at ix + 1,
+// borders of M are zero), so no bounds test is needed inside the loop.
+// ---------------------------------------------------------------------------
+template <int UP>
+__global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
+                                               int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
+                                               float step, long long vol_pad, float *__restrict__ I)
+{
+    const int p = blockIdx.z, s = s0 + p;
+    const int j = blockIdx.y * 16 + (threadIdx.x & 15);
+    const int k = blockIdx.x * 16 + (threadIdx.x >> 4);
+    if (j >= nj || k >= nk) return;
+    const ProjFrame &f = frames[s];
+    const double n3[3] = {(double)nx, (double)ny, (double)nz};
+    double b[3], ds[3];
+    double tlo = -1e300, thi = 1e300;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b[a] = f.o[a] + j * f.ej[a] + k * f.ek[a] + 0.5 * (n3[a] + 1.0);
+        ds[a] = (double)step * f.d[a];
+        if (f.inv_d[a] != 0.0) {
+            // index coordinate b + n ds must stay inside (0, n + 1)
+            double ia = f.inv_d[a] / (double)step;
+            double t1 = -b[a] * ia, t2 = (n3[a] + 1.0 - b[a]) * ia;
+            tlo = fmax(tlo, fmin(t1, t2));
+            thi = fmin(thi, fmax(t1, t2));
+        } else if (!(b[a] > 0.0 && b[a] < n3[a] + 1.0)) {
+            thi = -1e300;
+        }
+    }
+    float acc[UP];
+#pragma unroll
+    for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
+    if (tlo < thi) {
+        const int n0 = (int)ceil(tlo), n1 = (int)floor(thi);
+        const long long sz = UP, sy = (long long)(nz + 2) * UP, sx = (long long)(ny + 2) * sy;
+        const float *Mp = M + (long long)p * vol_pad * UP;
+        for (int n = n0; n <= n1; ++n) {
+            double px = fma((double)n, ds[0], b[0]);
+            double py = fma((double)n, ds[1], b[1]);
+            double pz = fma((double)n, ds[2], b[2]);
+            int ix = min(max((int)floor(px), 0), nx);
+            int iy = min(max((int)floor(py), 0), ny);
+            int iz = min(max((int)floor(pz), 0), nz);
+            float fx = (float)(px - ix), fy = (float)(py - iy), fz = (float)(pz - iz);
+            float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+            float w00 = gx * gy, w01 = gx * fy, w10 = fx * gy, w11 = fx * fy;
+            const float *q = Mp + ix * sx + iy * sy + iz * sz;
+            float w[8] = {w00 * gz, w00 * fz, w01 * gz, w01 * fz, w10 * gz, w10 * fz, w11 * gz, w11 * fz};
+            const long long off[8] = {0, sz, sy, sy + sz, sx, sx + sz, sx + sy, sx + sy + sz};
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+#pragma unroll
+                for (int u4 = 0; u4 < UP; u4 += 4) {
+                    f4 m = *reinterpret_cast<const f4 *>(q + off[cc] + u4);
+                    acc[u4 + 0] = fmaf(w[cc], m.x, acc[u4 + 0]);
+                    acc[u4 + 1] = fmaf(w[cc], m.y, acc[u4 + 1]);
+                    acc[u4 + 2] = fmaf(w[cc], m.z, acc[u4 + 2]);
+                    acc[u4 + 3] = fmaf(w[cc], m.w, acc[u4 + 3]);
+                }
+            }
+        }
+    }
+    float *out = I + (((long long)s * nj + j) * nk + k) * nseg;
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+        if (u < U) {
+            for (int cseg = u; cseg < nseg; cseg += U) out[cseg] = step * acc[u];
+        }
+    }
+}
+
+template <int UP>
+static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np, float *I,
+                          hipStream_t st)
+{
+    const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
+    dim3 grid((d.nk + 15) / 16, (d.nj + 15) / 16, np);
+    hipLaunchKernelGGL(k_march<UP>, grid, dim3(256), 0, st, M, frames, s0, d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg,
+                       d.U, d.step, vol_pad, I);
+    return hipGetLastError();
+}
+
+hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np, float *I,
+                        hipStream_t st)
+{
+    switch (d.Up) {
+    case 4: return march_t<4>(d, frames, M, s0, np, I, st);
+    case 8: return march_t<8>(d, frames, M, s0, np, I, st);
+    case 16: return march_t<16>(d, frames, M, s0, np, I, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fold: yf = scale * antipodal fold of y (zero beyond U).
+// ---------------------------------------------------------------------------
+template <int UP>
+__global__ __launch_bounds__(256) void k_fold(const float *__restrict__ y, long long npix, int nseg, int U,
+                                              float scale, float *__restrict__ yf)
+{
+    for (long long px = blockIdx.x * 256LL + threadIdx.x; px < npix; px += (long long)gridDim.x * 256) {
+        const float *yr = y + px * nseg;
+        float acc[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < UP; ++u)
+            if (u < U)
+                for (int cseg = u; cseg < nseg; cseg += U) acc[u] += yr[cseg];
+        f4 *o = reinterpret_cast<f4 *>(yf + px * UP);
+#pragma unroll
+        for (int u4 = 0; u4 < UP; u4 += 4)
+            o[u4 / 4] = f4{scale * acc[u4], scale * acc[u4 + 1], scale * acc[u4 + 2], scale * acc[u4 + 3]};
+    }
+}
+
+static int grid_for(long long n) { return (int)min((n + 255) / 256, 4096LL); }
+
+hipError_t launch_fold(const Dims &d, const float *y, float scale, float *yf, hipStream_t st)
+{
+    const long long npix = (long long)d.S * d.nj * d.nk;
+    const int g = grid_for(npix);
+    switch (d.Up) {
+    case 4: hipLaunchKernelGGL(k_fold<4>, dim3(g), dim3(256), 0, st, y, npix, d.nseg, d.U, scale, yf); break;
+    case 8: hipLaunchKernelGGL(k_fold<8>, dim3(g), dim3(256), 0, st, y, npix, d.nseg, d.U, scale, yf); break;
+    case 16: hipLaunchKernelGGL(k_fold<16>, dim3(g), dim3(256), 0, st, y, npix, d.nseg, d.U, scale, yf); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// r = Ip - data; yf = step * fold(2 w r); partial sums of w r^2 per block.
+template <int UP>
+__global__ __launch_bounds__(256) void k_residual_fold(const float *__restrict__ Ip, const float *__restrict__ data,
+                                                       const float *__restrict__ w, float *r, long long npix,
+                                                       int nseg, int U, float step, float *__restrict__ yf,
+                                                       double *__restrict__ partials)
+{
+    __shared__ double ws[4];
+    double loss = 0.0;
+    for (long long px = blockIdx.x * 256LL + threadIdx.x; px < npix; px += (long long)gridDim.x * 256) {
+        float acc[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            if (u < U) {
+                for (int cseg = u; cseg < nseg; cseg += U) {
+                    long long e = px * nseg + cseg;
+                    float rv = Ip[e] - data[e];
+                    float wv = w ? w[e] : 1.0f;
+                    if (r) r[e] = rv;
+                    loss += (double)wv * (double)rv * (double)rv;
+                    acc[u] += 2.0f * wv * rv;
+                }
+            }
+        }
+        f4 *o = reinterpret_cast<f4 *>(yf + px * UP);
+#pragma unroll
+        for (int u4 = 0; u4 < UP; u4 += 4)
+            o[u4 / 4] = f4{step * acc[u4], step * acc[u4 + 1], step * acc[u4 + 2], step * acc[u4 + 3]};
+    }
+    double tot = block_sum(loss, ws);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *data, const float *w, float *r,
+                                float *yf, double *partials, int nblocks, hipStream_t st)
+{
+    const long long npix = (long long)d.S * d.nj * d.nk;
+    switch (d.Up) {
+    case 4:
+        hipLaunchKernelGGL(k_residual_fold<4>, dim3(nblocks), dim3(256), 0, st, Ip, data, w, r, npix, d.nseg, d.U,
+                           d.step, yf, partials);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_residual_fold<8>, dim3(nblocks), dim3(256), 0, st, Ip, data, w, r, npix, d.nseg, d.U,
+                           d.step, yf, partials);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_residual_fold<16>, dim3(nblocks), dim3(256), 0, st, Ip, data, w, r, npix, d.nseg,
+                           d.U, d.step, yf, partials);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// backproject: block = brick of 4 (x) x 8 (y) x 8 (z) voxels; wave w owns the
+// x-slice w (64 voxels = 4 column tiles of 16).  Loops over all projections.
+// ---------------------------------------------------------------------------
+template <int UP, int MT>
+__global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ yf, const ProjFrame *__restrict__ frames,
+                                                     const float *__restrict__ Bu, int S, int nx, int ny, int nz,
+                                                     int nj, int nk, int C, int Cp, float step,
+                                                     float *__restrict__ g, float beta, const float *__restrict__ c,
+                                                     double *__restrict__ partials)
+{
+    __shared__ float Qs[4][64 * (UP + 1)];
+    __shared__ double ws[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nbx = (nx + 3) / 4, nby = (ny + 7) / 8;
+    const int bid = blockIdx.x;
+    const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+    const int ix = bx * 4 + wave, iy = by * 8 + (lane >> 3), iz = bz * 8 + (lane & 7);
+    const bool valid = ix < nx && iy < ny && iz < nz;
+    const double xv[3] = {ix - 0.5 * (nx - 1), iy - 0.5 * (ny - 1), iz - 0.5 * (nz - 1)};
+    const double dstep = (double)step, inv_step = 1.0 / dstep;
+
+    f4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+
+    float *Qw = Qs[wave];
+    for (int s = 0; s < S; ++s) {
+        const ProjFrame &f = frames[s];
+        float q[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) q[u] = 0.0f;
+        if (valid) {
+            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+            const double t = w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2];
+            const int jlo = max(0, (int)ceil(a - f.lj)), jhi = min(nj - 1, (int)floor(a + f.lj));
+            const int klo = max(0, (int)ceil(bb - f.lk)), khi = min(nk - 1, (int)floor(bb + f.lk));
+            for (int j = jlo; j <= jhi; ++j) {
+                const double dj = j - a;
+                for (int k = klo; k <= khi; ++k) {
+                    const double dk = k - bb;
+                    double P[3];
+                    double tlo = -1e300, thi = 1e300;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        P[m] = dj * f.ej[m] + dk * f.ek[m];
+                        if (f.inv_d[m] != 0.0) {
+                            double t1 = (-1.0 - P[m]) * f.inv_d[m], t2 = (1.0 - P[m]) * f.inv_d[m];
+                            tlo = fmax(tlo, fmin(t1, t2));
+                            thi = fmin(thi, fmax(t1, t2));
+                        } else if (fabs(P[m]) >= 1.0) {
+                            thi = -1e300;
+                        }
+                    }
+                    if (!(tlo < thi)) continue;
+                    const int n0 = (int)ceil((t + tlo) * inv_step), n1 = (int)floor((t + thi) * inv_step);
+                    if (n0 > n1) continue;
+                    const f4 *yp = reinterpret_cast<const f4 *>(yf + (((long long)s * nj + j) * nk + k) * UP);
+                    float wsum = 0.0f;
+                    for (int n = n0; n <= n1; ++n) {
+                        const double tau = n * dstep - t;
+                        double wt = 1.0;
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) wt *= fmax(0.0, 1.0 - fabs(fma(tau, f.d[m], P[m])));
+                        wsum += (float)wt;
+                    }
+#pragma unroll
+                    for (int u4 = 0; u4 < UP; u4 += 4) {
+                        f4 yv = yp[u4 / 4];
+                        q[u4 + 0] = fmaf(wsum, yv.x, q[u4 + 0]);
+                        q[u4 + 1] = fmaf(wsum, yv.y, q[u4 + 1]);
+                        q[u4 + 2] = fmaf(wsum, yv.z, q[u4 + 2]);
+                        q[u4 + 3] = fmaf(wsum, yv.w, q[u4 + 3]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UP; ++u) Qw[lane * (UP + 1) + u] = q[u];
+        __syncthreads();
+        // g tile += B_s^T (coefficients x u) * Q^T (u x voxels)
+        const float *Bs = Bu + (long long)s * UP * Cp;
+#pragma unroll
+        for (int ks = 0; ks < UP / 4; ++ks) {
+            float av[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) av[mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                float bv = Qw[(nt * 16 + (lane & 15)) * (UP + 1) + ks * 4 + (lane >> 4)];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(av[mt], bv, acc[mt][nt]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: lane holds rows (coefficients) 16 mt + 4 (lane/16) + r of voxel column 16 nt + lane % 16
+    double c2 = 0.0;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int lv = nt * 16 + (lane & 15);
+        const int vy = by * 8 + (lv >> 3), vz = bz * 8 + (lv & 7);
+        if (ix < nx && vy < ny && vz < nz) {
+            const long long base = (((long long)ix * ny + vy) * nz + vz) * C;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mt * 16 + 4 * (lane >> 4) + r;
+                    if (i < C) {
+                        float val = acc[mt][nt][r];
+                        if (c) {
+                            float cv = c[base + i];
+                            val += beta * cv;
+                            c2 += (double)cv * (double)cv;
+                        }
+                        g[base + i] = val;
+                    }
+                }
+            }
+        }
+    }
+    if (partials) {
+        double tot = block_sum(c2, ws);
+        if (tid == 0) partials[bid] = tot;
+    }
+}
+
+int backproject_blocks(const Dims &d) { return ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
+
+template <int UP, int MT>
+static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu, float *g,
+                       float beta, const float *c, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_backproject<UP, MT>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames, Bu, d.S,
+                       d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    return hipGetLastError();
+}
+
+template <int UP>
+static hipError_t bp_mt(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu, float *g,
+                        float beta, const float *c, double *partials, hipStream_t st)
+{
+    switch (d.Cp / 16) {
+    case 1: return bp_t<UP, 1>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 2: return bp_t<UP, 2>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 3: return bp_t<UP, 3>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 4: return bp_t<UP, 4>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 5: return bp_t<UP, 5>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 6: return bp_t<UP, 6>(d, frames, yf, Bu, g, beta, c, partials, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu,
+                              const uint16_t *, int bf16, float *g, float beta, const float *c, double *partials,
+                              hipStream_t st)
+{
+    if (bf16) return hipErrorNotSupported;
+    switch (d.Up) {
+    case 4: return bp_mt<4>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 8: return bp_mt<8>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 16: return bp_mt<16>(d, frames, yf, Bu, g, beta, c, partials, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// out[0] (+)= scale * sum(partials[0..n))
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ partials, int n, double *out,
+                                                      double scale, int accumulate)
+{
+    __shared__ double ws[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += partials[i];
+    double tot = block_sum(v, ws);
+    if (threadIdx.x == 0) out[0] = (accumulate ? out[0] : 0.0) + scale * tot;
+}
+
+hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale, int accumulate,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, n, out, scale, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace tt

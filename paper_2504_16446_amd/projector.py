@@ -1,0 +1,236 @@
+"""Python face of the C ABI: projector, autograd function and L-BFGS solver.
+
+Argument marshalling only.  PyTorch provides device memory and the current
+HIP stream; every step of the computation runs in ``libtt_hip.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib, synth
+from ._lib import Geometry, call, lib
+
+__all__ = ["Projector", "ProjectFn", "project", "LBFGS", "sh_eval", "num_coeffs"]
+
+
+def num_coeffs(ell_max: int) -> int:
+    return call("tt_num_coeffs", int(ell_max))
+
+
+def sh_eval(ell_max: int, dirs) -> np.ndarray:
+    """Real even-order spherical harmonics at directions ``dirs[..., 3]`` (host)."""
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((d.shape[0], num_coeffs(ell_max)))
+    call("tt_sh_eval", int(ell_max), d.shape[0], d.ctypes.data_as(C.POINTER(C.c_double)),
+         out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out.reshape(np.shape(dirs)[:-1] + (out.shape[1],))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _f32(t: torch.Tensor, shape, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32 or t.device != device:
+        raise ValueError(f"{name} must be float32 on {device}, got {t.dtype} on {t.device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Projector:
+    """Forward model I = A c, adjoint and loss gradient for one geometry.
+
+    Shapes: coefficients ``(nx, ny, nz, C)``, data ``(n_proj, nj, nk, n_seg)``.
+    """
+
+    def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame=None, n_sub=3, step=1.0,
+                 seg_span=2 * math.pi, joff=None, koff=None, map_precision="fp32", device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("Projector runs on a HIP device only")
+        frame = synth.lab_frame() if frame is None else frame
+        self._keep = [np.ascontiguousarray(inner, dtype=np.float64),
+                      np.ascontiguousarray(outer, dtype=np.float64),
+                      None if joff is None else np.ascontiguousarray(joff, dtype=np.float64),
+                      None if koff is None else np.ascontiguousarray(koff, dtype=np.float64)]
+        if len(self._keep[0]) != len(self._keep[1]):
+            raise ValueError("inner and outer angle arrays differ in length")
+        g = Geometry()
+        g.nx, g.ny, g.nz = (int(v) for v in n)
+        g.ell_max, g.n_proj = int(ell_max), len(self._keep[0])
+        g.nj, g.nk, g.n_seg, g.n_sub = int(nj), int(nk), int(n_seg), int(n_sub)
+        g.map_precision = _lib.TT_MAP_BF16 if map_precision == "bf16" else _lib.TT_MAP_FP32
+        g.step, g.seg_span = float(step), float(seg_span)
+        g.inner_angle, g.outer_angle = _dptr(self._keep[0]), _dptr(self._keep[1])
+        g.j_offset, g.k_offset = _dptr(self._keep[2]), _dptr(self._keep[3])
+        for field, key in (("p", "p"), ("j", "j"), ("k", "k"), ("q0", "q0"), ("q90", "q90"),
+                           ("alpha_axis", "alpha"), ("beta_axis", "beta")):
+            getattr(g, field)[:] = [float(x) for x in frame[key]]
+        self.geometry = g
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            call("tt_create", C.byref(g), C.byref(handle))
+        self._h = handle
+        sizes = (C.c_int64 * 6)()
+        call("tt_sizes", self._h, sizes)
+        self.n = tuple(int(v) for v in n)
+        self.ell_max, self.n_proj = int(ell_max), g.n_proj
+        self.nj, self.nk, self.n_seg = int(nj), int(nk), int(n_seg)
+        self.n_coeff, self.n_unique, self.batch, self.work_bytes = (
+            int(sizes[2]), int(sizes[3]), int(sizes[4]), int(sizes[5]))
+        self.precision = map_precision
+
+    @classmethod
+    def from_workload(cls, w: synth.Workload, **kw):
+        inner, outer = synth.angles(w)
+        return cls(w.n, w.ell_max, inner, outer, w.nj, w.nk, w.n_seg, n_sub=w.n_sub, step=w.step, **kw)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().tt_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def vol_shape(self):
+        return self.n + (self.n_coeff,)
+
+    @property
+    def data_shape(self):
+        return (self.n_proj, self.nj, self.nk, self.n_seg)
+
+    def set_precision(self, precision: str):
+        call("tt_set_map_precision", self._h,
+             _lib.TT_MAP_BF16 if precision == "bf16" else _lib.TT_MAP_FP32)
+        self.precision = precision
+
+    def timing(self, on: bool = True):
+        """Start (or stop) per-kernel-class event timing on this projector's stream."""
+        call("tt_timing_enable", self._h, int(bool(on)))
+
+    def timing_read(self):
+        """{class: (total_ms, launches)} since the last read; synchronises."""
+        ms = (C.c_double * len(_lib.KERNEL_CLASSES))()
+        n = (C.c_int64 * len(_lib.KERNEL_CLASSES))()
+        call("tt_timing_read", self._h, ms, n)
+        return {k: (ms[i], int(n[i])) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+    def basis_matrix(self) -> np.ndarray:
+        B = np.empty((self.n_proj, self.n_seg, self.n_coeff))
+        call("tt_basis_matrix", self._h, _dptr(B))
+        return B
+
+    def _bind_stream(self):
+        call("tt_set_stream", self._h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def forward(self, c: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        pc = _f32(c, self.vol_shape, "c", self.device)
+        if out is None:
+            out = torch.empty(self.data_shape, dtype=torch.float32, device=self.device)
+        po = _f32(out, self.data_shape, "out", self.device)
+        self._bind_stream()
+        call("tt_project", self._h, pc, po)
+        return out
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None, beta: float = 0.0,
+                c: torch.Tensor | None = None) -> torch.Tensor:
+        py = _f32(y, self.data_shape, "y", self.device)
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=torch.float32, device=self.device)
+        po = _f32(out, self.vol_shape, "out", self.device)
+        pcv = _f32(c, self.vol_shape, "c", self.device) if c is not None else None
+        self._bind_stream()
+        call("tt_adjoint", self._h, py, po, float(beta), pcv)
+        return out
+
+    def loss_grad(self, c, data, w=None, mu=0.0, want_resid=True):
+        """(loss[1] float64, grad, resid) of sum w (Ac - I)^2 + mu sum c^2."""
+        pc = _f32(c, self.vol_shape, "c", self.device)
+        pd = _f32(data, self.data_shape, "data", self.device)
+        pw = _f32(w, self.data_shape, "w", self.device) if w is not None else None
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        grad = torch.empty(self.vol_shape, dtype=torch.float32, device=self.device)
+        resid = torch.empty(self.data_shape, dtype=torch.float32, device=self.device) if want_resid else None
+        self._bind_stream()
+        call("tt_loss_grad", self._h, pc, pd, pw, float(mu), C.c_void_p(loss.data_ptr()),
+             C.c_void_p(grad.data_ptr()), C.c_void_p(resid.data_ptr()) if resid is not None else None)
+        return loss, grad, resid
+
+
+class ProjectFn(torch.autograd.Function):
+    """Differentiable I = A c: the backward pass is the library's exact adjoint."""
+
+    @staticmethod
+    def forward(ctx, c, projector: Projector):
+        ctx.projector = projector
+        return projector.forward(c.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        return ctx.projector.adjoint(grad_out.contiguous()), None
+
+
+def project(c: torch.Tensor, projector: Projector) -> torch.Tensor:
+    return ProjectFn.apply(c, projector)
+
+
+class LBFGS:
+    """Device-resident L-BFGS on sum w (Ac - I)^2 + mu sum c^2 (exact line search)."""
+
+    def __init__(self, projector: Projector, m: int = 10):
+        self.projector = projector
+        h = C.c_void_p()
+        call("tt_lbfgs_create", projector._h, int(m), C.byref(h))
+        self._h = h
+        self.m = m
+        self._refs = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().tt_lbfgs_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def init(self, c: torch.Tensor, data: torch.Tensor, w: torch.Tensor | None = None, mu: float = 0.0):
+        p = self.projector
+        pc = _f32(c, p.vol_shape, "c", p.device)
+        pd = _f32(data, p.data_shape, "data", p.device)
+        pw = _f32(w, p.data_shape, "w", p.device) if w is not None else None
+        self._refs = (c, data, w)  # the solver reads these buffers on every step
+        p._bind_stream()
+        call("tt_lbfgs_init", self._h, pc, pd, pw, float(mu))
+
+    def step(self):
+        self.projector._bind_stream()
+        call("tt_lbfgs_step", self._h)
+
+    def query(self):
+        """(loss, ||r||, ||I||, accepted pairs); synchronises."""
+        out = (C.c_double * 4)()
+        self.projector._bind_stream()
+        call("tt_lbfgs_query", self._h, out)
+        return tuple(out)
+
+    def run(self, max_iter: int, rel_tol: float = 0.0):
+        """Iterate; returns (iterations, history[iters, 2] of (loss, ||r||/||I||))."""
+        hist = np.zeros((max(max_iter, 1), 2))
+        it = C.c_int(0)
+        self.projector._bind_stream()
+        call("tt_lbfgs_run", self._h, int(max_iter), float(rel_tol),
+             hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(it))
+        return it.value, hist[: it.value]

@@ -1,0 +1,104 @@
+"""Differentiation: ProjectFn's backward is the library's adjoint.
+
+Checked against the oracle gradient and against float64 central differences
+of the oracle loss on coordinate directions (a quadratic, so the difference
+quotient is exact up to rounding; only rays that touch the perturbed voxel
+change, and those are recomputed by the oracle ray by ray).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import phantom
+from geoms import small, workload
+from helpers import gpu_projector, rel_l2
+from paper_2504_16446_amd import synth
+from paper_2504_16446_amd.projector import project
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32), device=DEV)
+
+
+def test_autograd_matches_oracle_gradient():
+    og = small(ell_max=8, n_seg=16)
+    rng = np.random.default_rng(21)
+    c = rng.standard_normal(og.vol_shape).astype(np.float32).astype(np.float64)
+    data = rng.standard_normal(og.data_shape).astype(np.float32).astype(np.float64)
+    P = gpu_projector(og)
+    ct = _t(c).requires_grad_(True)
+    I = project(ct, P)
+    loss = ((I.double() - _t(data).double()) ** 2).sum() + 1e-3 * (ct.double() ** 2).sum()
+    loss.backward()
+    _, g_ref, _ = oracle.loss_grad(og, c, data, None, 1e-3)
+    assert rel_l2(ct.grad.cpu().numpy(), g_ref) <= 1e-5
+    # torch's own check of the backward against the forward (linear map)
+    y = torch.randn(og.data_shape, device=DEV)
+    v = torch.randn(og.vol_shape, device=DEV)
+    lhs = (project(v, P).double() * y.double()).sum()
+    rhs = (v.double() * P.adjoint(y).double()).sum()
+    assert abs(float(lhs - rhs)) <= 1e-5 * float(lhs.abs() + rhs.abs() + 1)
+
+
+def _fd_directions(og, c, data, mu, idx, h):
+    """float64 central differences of the oracle loss along coordinate directions."""
+    out = []
+    for (ix, iy, iz, i) in idx:
+        rays = []
+        xv = np.array([ix, iy, iz]) - (np.array(og.n) - 1) / 2
+        for s in range(og.n_proj):
+            ej, ek, d, o = oracle.frame(og, s)
+            a, b = (xv - o) @ ej, (xv - o) @ ek
+            for j in range(int(np.floor(a)) - 2, int(np.floor(a)) + 4):
+                for k in range(int(np.floor(b)) - 2, int(np.floor(b)) + 4):
+                    if 0 <= j < og.nj and 0 <= k < og.nk:
+                        rays.append((s, j, k))
+        rays = np.array(rays, dtype=np.int32)
+        cp, cm = c.copy(), c.copy()
+        cp[ix, iy, iz, i] += h
+        cm[ix, iy, iz, i] -= h
+        dsel = data[rays[:, 0], rays[:, 1], rays[:, 2]]
+        rp = oracle.project_rays(og, cp, rays) - dsel
+        rm = oracle.project_rays(og, cm, rays) - dsel
+        num = np.sum((rp - rm) * (rp + rm)) + mu * (cp[ix, iy, iz, i] ** 2 - cm[ix, iy, iz, i] ** 2)
+        out.append(num / (2 * h))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("name", ["small", "c3"])
+def test_gradient_vs_float64_finite_differences(name):
+    if name == "c3":
+        w = synth.WORKLOADS["c3"]
+        og = workload("c3")
+        rng = np.random.default_rng(w.seed_phantom + 7)
+        c = 0.5 * phantom.phantom_coeffs(w) + 0.01 * rng.standard_normal(og.vol_shape)
+        n_dir = 64
+        _, _, density = synth.twisted_fibre_field(w)
+        support = np.argwhere(density > 0)
+    else:
+        og = small(ell_max=4)
+        rng = np.random.default_rng(5)
+        c = rng.standard_normal(og.vol_shape)
+        n_dir = 16
+        support = np.argwhere(np.ones(og.n, bool))
+    c = c.astype(np.float32).astype(np.float64)
+    data = rng.standard_normal(og.data_shape).astype(np.float32).astype(np.float64)
+    mu = 1e-3
+    pick = support[rng.integers(0, len(support), n_dir)]
+    idx = [(int(v[0]), int(v[1]), int(v[2]), int(rng.integers(0, og.n_coeff))) for v in pick]
+    fd = _fd_directions(og, c, data, mu, idx, 1e-6)
+    P = gpu_projector(og)
+    ct = _t(c).requires_grad_(True)
+    I = project(ct, P)
+    loss = ((I.double() - _t(data).double()) ** 2).sum() + mu * (ct.double() ** 2).sum()
+    loss.backward()
+    g = ct.grad.cpu().numpy().astype(np.float64)
+    got = np.array([g[v] for v in idx])
+    scale = np.abs(g).max()
+    err = np.abs(got - fd) / scale
+    print(name, "max |grad - fd| / max|grad|", err.max())
+    assert err.max() <= 1e-5
