@@ -123,6 +123,8 @@ def main():
                     help="plain L-BFGS iterations for time-to-residual (default: the workload's)")
     ap.add_argument("--cpu-sample", type=int, default=12, help="projections in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -139,6 +141,15 @@ def main():
     torch.cuda.set_device(dev)
     print(f"[bench] workload {w.name}: {w.n} ell_max {w.ell_max} S={w.n_proj} "
           f"detector {w.nj}x{w.nk}x{w.n_seg}", file=sys.stderr, flush=True)
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     P = Projector.from_workload(w, device=dev)
     c_true_np = phantom.coefficients(w)
