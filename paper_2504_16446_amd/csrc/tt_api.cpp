@@ -42,6 +42,7 @@ struct tt_ctx {
     std::vector<double> B;  // [S][nseg][C] float64
     ProjFrame *d_frames = nullptr;
     float *d_Bu = nullptr;      // [bu_rows][Cp]: row s*Up + u, zero padded
+    float *d_Bsw = nullptr;     // Bu in MFMA lane order (16-row tiles), for the forward map
     uint16_t *d_Bu16 = nullptr; // bf16 copy (same layout)
     int pb = 1;                 // projections per forward batch
     long long vol_pad = 0;
@@ -261,6 +262,16 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     size_t budget = (size_t)1 << 30;
     if (const char *e = std::getenv("TT_FORWARD_BATCH_BYTES")) budget = (size_t)std::strtoull(e, nullptr, 10);
     c->pb = (int)std::max<size_t>(1, std::min<size_t>((size_t)S, budget / per_proj));
+    // batches start on a 16-row tile of (projection, segment) rows
+    const int align = 16 / d.Up;
+    if (c->pb < S) c->pb = std::max(align, c->pb / align * align);
+    // MFMA-ordered copy of Bu: tile rt, k-step ks, lane l -> Bu[16 rt + l % 16][4 ks + l / 16]
+    std::vector<float> bsw(bu.size(), 0.0f);
+    const int KS = d.Cp / 4;
+    for (int rt = 0; rt < bu_rows / 16; ++rt)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int l = 0; l < 64; ++l)
+                bsw[((size_t)rt * KS + ks) * 64 + l] = bu[((size_t)rt * 16 + l % 16) * d.Cp + 4 * ks + l / 16];
     c->n_part = 1024 + std::max(4096, backproject_blocks(d));
     const size_t yf_bytes = (size_t)S * d.nj * d.nk * d.Up * sizeof(float);
 
@@ -270,6 +281,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     };
     if (hipMalloc(&c->d_frames, sizeof(ProjFrame) * S) != hipSuccess ||
         hipMalloc(&c->d_Bu, bu.size() * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_Bsw, bsw.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bu16, bu16.size() * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc(&c->d_M, per_proj * c->pb) != hipSuccess || hipMalloc(&c->d_yf, yf_bytes) != hipSuccess ||
         hipMalloc(&c->d_part, sizeof(double) * c->n_part) != hipSuccess)
@@ -277,6 +289,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     c->work_bytes = per_proj * c->pb + yf_bytes + sizeof(double) * c->n_part + bu.size() * 6;
     if (hipMemcpy(c->d_frames, c->frames.data(), sizeof(ProjFrame) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bu, bu.data(), bu.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_Bsw, bsw.data(), bsw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bu16, bu16.data(), bu16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_M, 0, per_proj * c->pb) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return cleanup(TT_EHIP, "device upload failed");
@@ -290,6 +303,7 @@ void tt_destroy(tt_ctx *c)
     tt_timing_enable(c, 0);
     hipFree(c->d_frames);
     hipFree(c->d_Bu);
+    hipFree(c->d_Bsw);
     hipFree(c->d_Bu16);
     hipFree(c->d_M);
     hipFree(c->d_yf);
@@ -373,7 +387,7 @@ static int project_impl(tt_ctx *c, const float *cin, float *I)
         {
             KTimer t(c, TT_K_MAP);
             e = c->precision == TT_MAP_BF16 ? launch_map_bf16(c->d, cin, c->d_Bu16, s0, np, c->d_M, c->stream)
-                                            : launch_map_fp32(c->d, cin, c->d_Bu, s0, np, c->d_M, c->stream);
+                                            : launch_map_fp32(c->d, cin, c->d_Bsw, s0, np, c->d_M, c->stream);
         }
         if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
                                          std::string("map: ") + hipGetErrorString(e));

@@ -22,6 +22,7 @@
 // (small-angle form of Eq. 1), segment c centred at c * span / n_seg.
 #include "tt_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -102,6 +103,55 @@ void rotate_inverse(const Quat &q, const double *v, double *out)
     out[2] = v[2] + q.w * tz + (ux * ty - uy * tx);
 }
 
+// Upper and lower chains of the shadow of the cube [-1, 1]^3 (the zonotope
+// spanned by the three projected edges) as (slope, intercept) lines in y.
+void cube_shadow(const double *ej, const double *ek, float *hull)
+{
+    std::vector<std::pair<double, double>> pts;
+    for (int m = 0; m < 8; ++m) {
+        double sx = (m & 1) ? 1 : -1, sy = (m & 2) ? 1 : -1, sz = (m & 4) ? 1 : -1;
+        pts.push_back({sx * ej[0] + sy * ej[1] + sz * ej[2], sx * ek[0] + sy * ek[1] + sz * ek[2]});
+    }
+    std::sort(pts.begin(), pts.end());
+    auto cross = [](std::pair<double, double> o, std::pair<double, double> a, std::pair<double, double> b) {
+        return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
+    };
+    std::vector<std::pair<double, double>> lo, up;
+    for (auto &q : pts) {
+        while (lo.size() >= 2 && cross(lo[lo.size() - 2], lo.back(), q) <= 0) lo.pop_back();
+        lo.push_back(q);
+        while (up.size() >= 2 && cross(up[up.size() - 2], up.back(), q) >= 0) up.pop_back();
+        up.push_back(q);
+    }
+    auto lines = [](const std::vector<std::pair<double, double>> &ch, float *out, double fallback) {
+        int n = 0;
+        for (size_t i = 0; i + 1 < ch.size() && n < 3; ++i) {
+            double dy = ch[i + 1].first - ch[i].first;
+            if (dy < 1e-9) continue;  // vertical edge: bounds y only
+            double sl = (ch[i + 1].second - ch[i].second) / dy;
+            out[2 * n] = (float)sl;
+            out[2 * n + 1] = (float)(ch[i].second - sl * ch[i].first);
+            ++n;
+        }
+        if (n == 0) {
+            out[0] = 0.0f;
+            out[1] = (float)fallback;
+            n = 1;
+        }
+        for (int i = n; i < 3; ++i) {
+            out[2 * i] = out[0];
+            out[2 * i + 1] = out[1];
+        }
+    };
+    double zmax = -1e300, zmin = 1e300;
+    for (auto &q : pts) {
+        zmax = std::max(zmax, q.second);
+        zmin = std::min(zmin, q.second);
+    }
+    lines(up, hull, zmax);
+    lines(lo, hull + 6, zmin);
+}
+
 }  // namespace
 
 void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector<double> &B)
@@ -122,6 +172,13 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
         f.lj = std::fabs(f.ej[0]) + std::fabs(f.ej[1]) + std::fabs(f.ej[2]);
         f.lk = std::fabs(f.ek[0]) + std::fabs(f.ek[1]) + std::fabs(f.ek[2]);
         for (int a = 0; a < 3; ++a) f.inv_d[a] = std::fabs(f.d[a]) > 1e-12 ? 1.0 / f.d[a] : 0.0;
+        cube_shadow(f.ej, f.ek, f.hull);
+        for (int a = 0; a < 3; ++a) {
+            f.ejf[a] = (float)f.ej[a];
+            f.ekf[a] = (float)f.ek[a];
+            f.df[a] = (float)f.d[a];
+            f.inv_df[a] = (float)f.inv_d[a];
+        }
         for (int c = 0; c < g.n_seg; ++c) {
             double *row = &B[((size_t)s * g.n_seg + c) * C];
             for (int m = 0; m < g.n_sub; ++m) {

@@ -26,6 +26,13 @@ struct ProjFrame {
     double ej[3], ek[3], d[3];
     double inv_d[3];  // 1 / d_a, or 0 when the ray is parallel to plane a
     double lj, lk;    // L1 norms of e_j and e_k (bounds of the pixel window)
+    // Shadow of the cube [-1, 1]^3 on the detector plane in (j, k) offsets:
+    // for a row offset y = j - a the rays that can meet the cube have
+    // k - b in [max_i(lo_i y + lo_i'), min_i(up_i y + up_i')] (hull[0..5] the
+    // upper chain as (slope, intercept) pairs, hull[6..11] the lower chain).
+    float hull[12];
+    float ejf[3], ekf[3], df[3];  // float copies for the small offsets inside the cube
+    float inv_df[3];              // 1 / d_a or 0
 };
 
 int num_coeffs(int ell_max);

@@ -39,13 +39,17 @@ __device__ __forceinline__ long long pad_index(int v, int ny, int nz)
 }
 
 // ---------------------------------------------------------------------------
-// map (fp32 MFMA).  Block = 64 voxels x 256 rows (row = p * UP + u).
-// Each wave owns one 16-voxel column tile and loops over 16 row tiles.
+// map (fp32 MFMA).  Block = 64 voxels x 256 rows (row = p * UP + u), four
+// waves each owning 64 rows (4 row tiles) and all 4 voxel tiles, i.e. 16
+// independent 16x16 accumulators.  The c tile is staged transposed in LDS;
+// the B operands come from a copy of Bu pre-swizzled into MFMA lane order
+// (Bsw[(row_tile * Cp/4 + ks) * 64 + lane] = Bu[16 row_tile + lane % 16][4 ks + lane / 16]),
+// so every operand load is one coalesced 256-byte read.
 // ---------------------------------------------------------------------------
 constexpr int kCtStride = 80;  // padded voxel stride of the transposed c tile in LDS
 
 template <int UP>
-__global__ __launch_bounds__(256) void k_map_fp32(const float *__restrict__ c, const float *__restrict__ Bu,
+__global__ __launch_bounds__(256) void k_map_fp32(const float *__restrict__ c, const float *__restrict__ Bsw,
                                                   int V, int C, int Cp, int ny, int nz, int s0, int np,
                                                   long long vol_pad, float *__restrict__ M)
 {
@@ -54,60 +58,75 @@ __global__ __launch_bounds__(256) void k_map_fp32(const float *__restrict__ c, c
     const int v0 = blockIdx.x * 64;
     const int nv = min(64, V - v0);
     const float *cb = c + (long long)v0 * C;
-    for (int e = tid; e < 64 * Cp; e += 256) {
-        int k = e / 64, v = e % 64;
-        cT[k * kCtStride + v] = 0.0f;
-    }
+    for (int e = tid; e < 64 * Cp; e += 256) cT[(e >> 6) * kCtStride + (e & 63)] = 0.0f;
     __syncthreads();
+    const float invC = 1.0f / (float)C;
     for (int e = tid; e < nv * C; e += 256) {
-        int v = e / C, k = e - v * C;
+        int v = (int)(((float)e + 0.5f) * invC);
+        int k = e - v * C;
         cT[k * kCtStride + v] = cb[e];
     }
     __syncthreads();
 
-    const int col = wave * 16 + (lane & 15);  // voxel within block
+    const int KS = Cp / 4;
+    const int rt0 = (s0 * UP) / 16 + blockIdx.y * 16 + wave * 4;  // first row tile of this wave
     const int kq = lane >> 4;
-    const int v = v0 + col;
-    const long long vp = v < V ? pad_index(v, ny, nz) : 0;
-    const int row0 = blockIdx.y * 256;
-    const float *Bb = Bu + ((long long)s0 * UP + row0) * Cp;
-    for (int mt = 0; mt < 16; ++mt) {
-        const float *Ar = Bb + (long long)(mt * 16 + (lane & 15)) * Cp + kq;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < Cp / 4; ++ks) {
-            float a = Ar[ks * 4];
-            float b = cT[(ks * 4 + kq) * kCtStride + col];
-            acc = mfma16x16x4(a, b, acc);
+    f4 acc[4][4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < KS / 4; ++kc) {
+        float a[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) a[mt][kk] = Bsw[((long long)(rt0 + mt) * KS + kc * 4 + kk) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const float b = cT[(kc * 16 + kk * 4 + kq) * kCtStride + nt * 16 + (lane & 15)];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma16x16x4(a[mt][kk], b, acc[nt][mt]);
+            }
         }
-        const int row = row0 + mt * 16 + 4 * kq;  // first of the 4 rows held by this lane
-        const int p = row / UP, u0 = row % UP;
-        if (p < np && v < V) {
-            float *dst = M + (long long)p * vol_pad * UP + vp * UP + u0;
-            *reinterpret_cast<f4 *>(dst) = acc;
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int v = v0 + nt * 16 + (lane & 15);
+        if (v >= V) continue;
+        const long long vp = pad_index(v, ny, nz);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = blockIdx.y * 256 + wave * 64 + mt * 16 + 4 * kq;  // within the batch
+            const int p = row / UP, u0 = row % UP;
+            if (p < np) *reinterpret_cast<f4 *>(M + (long long)p * vol_pad * UP + vp * UP + u0) = acc[nt][mt];
         }
     }
 }
 
 template <int UP>
-static hipError_t map_fp32_t(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
+static hipError_t map_fp32_t(const Dims &d, const float *c, const float *Bsw, int s0, int np, float *M,
                              hipStream_t st)
 {
     const int V = d.nx * d.ny * d.nz;
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     dim3 grid((V + 63) / 64, (np * UP + 255) / 256);
     size_t lds = (size_t)d.Cp * kCtStride * sizeof(float);
-    hipLaunchKernelGGL(k_map_fp32<UP>, grid, dim3(256), lds, st, c, Bu, V, d.C, d.Cp, d.ny, d.nz, s0, np,
+    hipLaunchKernelGGL(k_map_fp32<UP>, grid, dim3(256), lds, st, c, Bsw, V, d.C, d.Cp, d.ny, d.nz, s0, np,
                        vol_pad, M);
     return hipGetLastError();
 }
 
-hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
+hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bsw, int s0, int np, float *M,
                            hipStream_t st)
 {
+    if ((s0 * d.Up) % 16) return hipErrorInvalidValue;  // batches start on a row tile
     switch (d.Up) {
-    case 4: return map_fp32_t<4>(d, c, Bu, s0, np, M, st);
-    case 8: return map_fp32_t<8>(d, c, Bu, s0, np, M, st);
-    case 16: return map_fp32_t<16>(d, c, Bu, s0, np, M, st);
+    case 4: return map_fp32_t<4>(d, c, Bsw, s0, np, M, st);
+    case 8: return map_fp32_t<8>(d, c, Bsw, s0, np, M, st);
+    case 16: return map_fp32_t<16>(d, c, Bsw, s0, np, M, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -343,41 +362,52 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
 #pragma unroll
         for (int u = 0; u < UP; ++u) q[u] = 0.0f;
         if (valid) {
+            // voxel centre in the ray frame (float64: magnitudes up to the volume size)
             const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
             const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
             const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
             const double t = w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2];
+            const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
             const int jlo = max(0, (int)ceil(a - f.lj)), jhi = min(nj - 1, (int)floor(a + f.lj));
-            const int klo = max(0, (int)ceil(bb - f.lk)), khi = min(nk - 1, (int)floor(bb + f.lk));
             for (int j = jlo; j <= jhi; ++j) {
-                const double dj = j - a;
+                // rays of this row that can meet the open cube around the voxel (float32 offsets < 2)
+                const float dj = (float)(j - a);
+                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, f.hull[1]), fmaf(f.hull[2], dj, f.hull[3])),
+                                         fmaf(f.hull[4], dj, f.hull[5]));
+                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, f.hull[7]), fmaf(f.hull[8], dj, f.hull[9])),
+                                         fmaf(f.hull[10], dj, f.hull[11]));
+                const int klo = max(0, (int)ceil(bb + (double)zmin - 1e-4));
+                const int khi = min(nk - 1, (int)floor(bb + (double)zmax + 1e-4));
+                const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
                 for (int k = klo; k <= khi; ++k) {
-                    const double dk = k - bb;
-                    double P[3];
-                    double tlo = -1e300, thi = 1e300;
+                    const float dk = (float)(k - bb);
+                    const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
+                    // parameter range along the ray inside the open cube: |P_m + tau d_m| < 1 for every axis
+                    float tlo = -3.0e38f, thi = 3.0e38f;
 #pragma unroll
                     for (int m = 0; m < 3; ++m) {
-                        P[m] = dj * f.ej[m] + dk * f.ek[m];
-                        if (f.inv_d[m] != 0.0) {
-                            double t1 = (-1.0 - P[m]) * f.inv_d[m], t2 = (1.0 - P[m]) * f.inv_d[m];
-                            tlo = fmax(tlo, fmin(t1, t2));
-                            thi = fmin(thi, fmax(t1, t2));
-                        } else if (fabs(P[m]) >= 1.0) {
-                            thi = -1e300;
+                        if (f.inv_df[m] != 0.0f) {
+                            const float cm = -P[m] * f.inv_df[m];
+                            tlo = fmaxf(tlo, cm - hinv[m]);
+                            thi = fminf(thi, cm + hinv[m]);
+                        } else if (fabsf(P[m]) >= 1.0f) {
+                            thi = -3.0e38f;
                         }
                     }
                     if (!(tlo < thi)) continue;
-                    const int n0 = (int)ceil((t + tlo) * inv_step), n1 = (int)floor((t + thi) * inv_step);
+                    const int n0 = (int)ceil((t + (double)tlo) * inv_step), n1 = (int)floor((t + (double)thi) * inv_step);
                     if (n0 > n1) continue;
-                    const f4 *yp = reinterpret_cast<const f4 *>(yf + (((long long)s * nj + j) * nk + k) * UP);
+                    float tau = (float)(n0 * dstep - t);
+                    const float stepf = (float)dstep;
                     float wsum = 0.0f;
                     for (int n = n0; n <= n1; ++n) {
-                        const double tau = n * dstep - t;
-                        double wt = 1.0;
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) wt *= fmax(0.0, 1.0 - fabs(fma(tau, f.d[m], P[m])));
-                        wsum += (float)wt;
+                        const float wx = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[0], P[0])));
+                        const float wy = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[1], P[1])));
+                        const float wz = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[2], P[2])));
+                        wsum = fmaf(wx * wy, wz, wsum);
+                        tau += stepf;
                     }
+                    const f4 *yp = reinterpret_cast<const f4 *>(yf + (((long long)s * nj + j) * nk + k) * UP);
 #pragma unroll
                     for (int u4 = 0; u4 < UP; u4 += 4) {
                         f4 yv = yp[u4 / 4];

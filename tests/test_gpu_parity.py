@@ -144,5 +144,5 @@ def test_forward_batches_agree():
         P2 = gpu_projector(og)
     finally:
         del os.environ["TT_FORWARD_BATCH_BYTES"]
-    assert P2.batch == 1 and P1.batch == og.n_proj
+    assert P2.batch <= 4 and P1.batch == og.n_proj
     assert torch.equal(P1.forward(_t(c)), P2.forward(_t(c)))
