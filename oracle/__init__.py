@@ -82,6 +82,7 @@ def _declare(L):
                            C.c_double, _dp, _dp, C.c_double]
     L.og_lbfgs.restype = C.c_int
     L.og_max_threads.restype = C.c_int
+    L.og_splat_projection.argtypes = [C.POINTER(Geom), C.c_int, _dp, C.c_int, _dp]
 
 
 def _p(a):
@@ -192,11 +193,62 @@ def basis_matrix(g: Geometry):
     return B
 
 
-def project(g: Geometry, c):
+def project(g: Geometry, c, B=None):
+    """I = A c; B overrides the basis constants (shape n_proj x n_seg x C)."""
     c = _f64(c)
     assert c.shape == g.vol_shape, (c.shape, g.vol_shape)
+    B = g.B() if B is None else _f64(B)
+    assert B.shape == (g.n_proj, g.n_seg, g.n_coeff)
     out = np.empty(g.data_shape)
-    lib().og_project(g.ref(), _p(g.B()), _p(c), _p(out))
+    lib().og_project(g.ref(), _p(B), _p(c), _p(out))
+    return out
+
+
+def splat_projection(g: Geometry, s: int, yf):
+    """Q[x, y, z, u] = sum over rays and samples of projection s of step * T * yf[j, k, u]."""
+    yf = _f64(yf)
+    nu = yf.shape[-1]
+    assert yf.shape == (g.nj, g.nk, nu)
+    Q = np.empty(g.n + (nu,))
+    lib().og_splat_projection(g.ref(), int(s), _p(yf), int(nu), _p(Q))
+    return Q
+
+
+def bf16(x):
+    """Round to bfloat16 (nearest even) through float32, returned as float64."""
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    u = x32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unique_segments(g: Geometry):
+    """Number of distinct segments: n_seg / 2 when the segments cover the full
+    circle (even orders make antipodal segments equal), else n_seg."""
+    full = abs(g.seg_span - 2 * np.pi) < 1e-12 and g.n_seg % 2 == 0
+    return g.n_seg // 2 if full else g.n_seg
+
+
+def adjoint_segment_first(g: Geometry, y, round_q=None, round_b=None):
+    """Adjoint evaluated as sum_s B_s^T Q_s with Q_s the splat of the folded y.
+
+    ``round_q`` / ``round_b`` (e.g. ``bf16``) are applied to Q_s and to the
+    unique-segment basis constants before the contraction, which reproduces
+    the rounding points of a reduced-precision map."""
+    y = _f64(y)
+    U = unique_segments(g)
+    yf = np.zeros(g.data_shape[:3] + (U,))
+    for cseg in range(g.n_seg):
+        yf[..., cseg % U] += y[..., cseg]
+    Bu = g.B()[:, :U, :]
+    if round_b is not None:
+        Bu = round_b(Bu)
+    out = np.zeros(g.vol_shape)
+    for s in range(g.n_proj):
+        Q = splat_projection(g, s, yf[s])
+        if round_q is not None:
+            Q = round_q(Q)
+        out += Q @ Bu[s]
     return out
 
 

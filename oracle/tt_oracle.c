@@ -439,6 +439,21 @@ void og_adjoint_voxels(const og_geom *g, const double *B, const double *y, int64
     }
 }
 
+/* Transpose of the ray sums of one projection on an arbitrary number of
+ * channels: Q[v][u] = sum_{j,k} sum_n step T(x_n - x_v) yf[j][k][u].  With
+ * yf the segment-folded residual this is the adjoint before the map by
+ * B_s^T; the precision-tier tests round Q at this point. */
+void og_splat_projection(const og_geom *g, int s, const double *yf, int nu, double *Q)
+{
+    og_frame f;
+    og_get_frame(g, s, &f);
+    int64_t nv = (int64_t)g->nx * g->ny * g->nz * nu;
+    memset(Q, 0, sizeof(double) * nv);
+    for (int j = 0; j < g->nj; ++j)
+        for (int k = 0; k < g->nk; ++k)
+            og_ray_splat(g, &f, j, k, yf + ((int64_t)j * g->nk + k) * nu, nu, Q);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Loss and gradient (Eqs. opt_prob_general_form and residual with a = b = 2,*/
 /* D = identity): r = A c - I, L = sum w r^2 + mu sum c^2,                   */

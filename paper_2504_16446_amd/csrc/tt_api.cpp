@@ -43,7 +43,8 @@ struct tt_ctx {
     ProjFrame *d_frames = nullptr;
     float *d_Bu = nullptr;      // [bu_rows][Cp]: row s*Up + u, zero padded
     float *d_Bsw = nullptr;     // Bu in MFMA lane order (16-row tiles), for the forward map
-    uint16_t *d_Bu16 = nullptr; // bf16 copy (same layout)
+    uint16_t *d_Bsw16 = nullptr; // bf16 Bu in MFMA lane order (16-row tiles, k blocks of 16), forward
+    uint16_t *d_BuT16 = nullptr; // bf16 [S][Cp][16]: B^T with u padded to 16, adjoint
     int pb = 1;                 // projections per forward batch
     long long vol_pad = 0;
     float *d_M = nullptr;       // [pb][vol_pad][Up]
@@ -249,14 +250,21 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     const int S = d.S;
     const int bu_rows = round_up(S * d.Up, 256) + 256;
     std::vector<float> bu((size_t)bu_rows * d.Cp, 0.0f);
-    std::vector<uint16_t> bu16((size_t)bu_rows * d.Cp, 0);
     for (int s = 0; s < S; ++s)
         for (int u = 0; u < d.U; ++u)
-            for (int i = 0; i < d.C; ++i) {
-                float v = (float)c->B[((size_t)s * d.nseg + u) * d.C + i];
-                bu[((size_t)s * d.Up + u) * d.Cp + i] = v;
-                bu16[((size_t)s * d.Up + u) * d.Cp + i] = to_bf16(v);
-            }
+            for (int i = 0; i < d.C; ++i) bu[((size_t)s * d.Up + u) * d.Cp + i] = (float)c->B[((size_t)s * d.nseg + u) * d.C + i];
+    // bf16 tables: forward operands in MFMA lane order, adjoint B^T with u padded to 16
+    const int KB = d.Cp / 16;
+    std::vector<uint16_t> bsw16(bu.size(), 0), but16((size_t)S * d.Cp * 16, 0);
+    for (int rt = 0; rt < bu_rows / 16; ++rt)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int l = 0; l < 64; ++l)
+                for (int q = 0; q < 4; ++q)
+                    bsw16[(((size_t)rt * KB + kb) * 64 + l) * 4 + q] =
+                        to_bf16(bu[((size_t)rt * 16 + l % 16) * d.Cp + 16 * kb + 4 * (l / 16) + q]);
+    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < d.Cp; ++i)
+            for (int u = 0; u < d.Up; ++u) but16[((size_t)s * d.Cp + i) * 16 + u] = to_bf16(bu[((size_t)s * d.Up + u) * d.Cp + i]);
     c->vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     const size_t per_proj = (size_t)c->vol_pad * d.Up * sizeof(float);
     size_t budget = (size_t)1 << 30;
@@ -282,15 +290,17 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     if (hipMalloc(&c->d_frames, sizeof(ProjFrame) * S) != hipSuccess ||
         hipMalloc(&c->d_Bu, bu.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bsw, bsw.size() * sizeof(float)) != hipSuccess ||
-        hipMalloc(&c->d_Bu16, bu16.size() * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&c->d_Bsw16, bsw16.size() * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&c->d_BuT16, but16.size() * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc(&c->d_M, per_proj * c->pb) != hipSuccess || hipMalloc(&c->d_yf, yf_bytes) != hipSuccess ||
         hipMalloc(&c->d_part, sizeof(double) * c->n_part) != hipSuccess)
         return cleanup(TT_ENOMEM, "device allocation failed");
-    c->work_bytes = per_proj * c->pb + yf_bytes + sizeof(double) * c->n_part + bu.size() * 6;
+    c->work_bytes = per_proj * c->pb + yf_bytes + sizeof(double) * c->n_part + bu.size() * 10 + but16.size() * 2;
     if (hipMemcpy(c->d_frames, c->frames.data(), sizeof(ProjFrame) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bu, bu.data(), bu.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bsw, bsw.data(), bsw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_Bu16, bu16.data(), bu16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_Bsw16, bsw16.data(), bsw16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_BuT16, but16.data(), but16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_M, 0, per_proj * c->pb) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return cleanup(TT_EHIP, "device upload failed");
     *out = c;
@@ -304,7 +314,8 @@ void tt_destroy(tt_ctx *c)
     hipFree(c->d_frames);
     hipFree(c->d_Bu);
     hipFree(c->d_Bsw);
-    hipFree(c->d_Bu16);
+    hipFree(c->d_Bsw16);
+    hipFree(c->d_BuT16);
     hipFree(c->d_M);
     hipFree(c->d_yf);
     hipFree(c->d_part);
@@ -386,7 +397,7 @@ static int project_impl(tt_ctx *c, const float *cin, float *I)
         hipError_t e;
         {
             KTimer t(c, TT_K_MAP);
-            e = c->precision == TT_MAP_BF16 ? launch_map_bf16(c->d, cin, c->d_Bu16, s0, np, c->d_M, c->stream)
+            e = c->precision == TT_MAP_BF16 ? launch_map_bf16(c->d, cin, c->d_Bsw16, s0, np, c->d_M, c->stream)
                                             : launch_map_fp32(c->d, cin, c->d_Bsw, s0, np, c->d_M, c->stream);
         }
         if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
@@ -411,7 +422,7 @@ static int backproject_impl(tt_ctx *c, float *g, float beta, const float *cin, d
     hipError_t e;
     {
         KTimer t(c, TT_K_BACKPROJECT);
-        e = launch_backproject(c->d, c->d_frames, c->d_yf, c->d_Bu, c->d_Bu16, c->precision == TT_MAP_BF16, g, beta,
+        e = launch_backproject(c->d, c->d_frames, c->d_yf, c->d_Bu, c->d_BuT16, c->precision == TT_MAP_BF16, g, beta,
                                cin, partials, c->stream);
     }
     if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
@@ -594,15 +605,13 @@ int tt_lbfgs_step(tt_lbfgs *st)
     {
         KTimer t(c, TT_K_VECTOR);
         TT_HIP(launch_sum_partials(p2, backproject_blocks(c->d), st->st + kCC, 1.0, 0, s));
-        TT_HIP(lbfgs_multidot(gnew, basis.data(), 2 * ns + 2, st->ist + kMask2, n, st->part, st->st + kDotsG, s));
+        // dots of the new gradient with the history, and y[cand] = g_new - g_old in the same pass
+        TT_HIP(lbfgs_multidot(gnew, basis.data(), 2 * ns + 2, st->ist + kMask2, n, st->part, st->st + kDotsG, s,
+                              basis.data() + ns, ns, st->ist, 2 * ns));
     }
     {
         KTimer t(c, TT_K_PLAN);
         TT_HIP(lbfgs_plan_update(st->st, st->ist, m, st->mu, s));
-    }
-    {
-        KTimer t(c, TT_K_VECTOR);
-        TT_HIP(lbfgs_make_y(basis.data() + ns, ns, st->ist, gnew, gold, n, s));
     }
     st->gcur = 1 - st->gcur;
     return TT_OK;

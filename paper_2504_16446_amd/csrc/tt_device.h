@@ -21,4 +21,16 @@ __device__ __forceinline__ double block_sum(double v, double *ws)
     return r;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Map the hardware block id to a logical id so that every XCD receives
+// one contiguous range of logical blocks: neighbouring tiles, which share
+// data, then share an L2.  A bijection on [0, nblk).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nblk)
+{
+    const int xcd = b % kNumXcd, idx = b / kNumXcd;
+    const int base = nblk / kNumXcd, extra = nblk % kNumXcd;
+    return xcd * base + min(xcd, extra) + idx;
+}
+
 }  // namespace tt

@@ -53,7 +53,7 @@ struct Dims {
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
 hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
                            hipStream_t st);
-hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bu16, int s0, int np,
+hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bsw16, int s0, int np,
                            float *M, hipStream_t st);
 // I[s0+p][j][k][c] = step * ray sums of M[p] along the rays of projection s0+p.
 hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np,
@@ -66,8 +66,10 @@ hipError_t launch_fold(const Dims &d, const float *y, float scale, float *yf, hi
 hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *data, const float *w,
                                 float *r, float *yf, double *partials, int nblocks, hipStream_t st);
 // g = A^T-part(yf) + beta c, with float64 partials of sum c^2 when c != null.
+// bf16 != 0: the transpose map runs on bf16 MFMA with Q rounded to bf16 and
+// BuT16[s][Cp][16] (bf16, u padded to 16 with zeros).
 hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const float *yf,
-                              const float *Bu, const uint16_t *Bu16, int bf16, float *g, float beta,
+                              const float *Bu, const uint16_t *BuT16, int bf16, float *g, float beta,
                               const float *c, double *partials, hipStream_t st);
 int backproject_blocks(const Dims &d);
 

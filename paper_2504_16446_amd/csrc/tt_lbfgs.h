@@ -42,8 +42,10 @@ hipError_t lbfgs_plan_alpha(double *st, int *ist, int m, double mu, hipStream_t 
 hipError_t lbfgs_plan_update(double *st, int *ist, int m, double mu, hipStream_t s);
 hipError_t lbfgs_combine(const float *const *basis, int nb, const double *coef, const int *mask, long long n,
                          float *d, double *partials, double *out, hipStream_t s);
+// Dot products x . vecs[a] (masked).  With y_slots, also y[cand] = x - vecs[gold].
 hipError_t lbfgs_multidot(const float *x, const float *const *vecs, int nv, const int *mask, long long n,
-                          double *partials, double *out, hipStream_t s);
+                          double *partials, double *out, hipStream_t s, const float *const *y_slots = nullptr,
+                          int ns = 0, const int *ist = nullptr, int gold = 0);
 hipError_t lbfgs_wnorm2(const float *q, const float *w, long long n, double *partials, double *out, hipStream_t s);
 hipError_t lbfgs_update_c(float *c, const float *d, const float *const *s_slots, int ns, const double *st,
                           const int *ist, long long n, hipStream_t s);

@@ -29,6 +29,25 @@ __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+typedef short s4 __attribute__((ext_vector_type(4)));  // four bf16 bit patterns
+
+// bf16 MFMA 16x16x16 (fp32 accumulate) operand layout (one wave):
+//   A[16][16]: lane l supplies A[l % 16][4 (l / 16) + q], q = 0..3
+//   B[16][16]: lane l supplies B[4 (l / 16) + q][l % 16]
+//   D as for the fp32 16x16x4 instruction.
+__device__ __forceinline__ f4 mfma16x16x16bf16(s4 a, s4 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// float -> bf16 bit pattern, round to nearest even (finite inputs).
+__device__ __forceinline__ short f2bf(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
 __device__ __forceinline__ long long pad_index(int v, int ny, int nz)
 {
     int iz = v % nz;
@@ -131,9 +150,89 @@ hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bsw, int 
     }
 }
 
-hipError_t launch_map_bf16(const Dims &, const float *, const uint16_t *, int, int, float *, hipStream_t)
+// ---------------------------------------------------------------------------
+// map, bf16 tier: c is rounded to bf16 while it is staged in LDS, B comes as
+// bf16 in MFMA lane order (Bsw16[(row_tile * Cp/16 + kb) * 64 + lane] holds
+// Bu[16 row_tile + lane % 16][16 kb + 4 (lane / 16) + q], q = 0..3), products
+// accumulate in fp32.  Same tiling as the fp32 kernel.
+// ---------------------------------------------------------------------------
+template <int UP>
+__global__ __launch_bounds__(256) void k_map_bf16(const float *__restrict__ c, const s4 *__restrict__ Bsw16,
+                                                  int V, int C, int Cp, int ny, int nz, int s0, int np,
+                                                  long long vol_pad, float *__restrict__ M)
 {
-    return hipErrorNotSupported;
+    extern __shared__ short cb[];  // [64][Cp + 4] bf16, row = voxel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ld = Cp + 4;
+    const int v0 = blockIdx.x * 64;
+    const int nv = min(64, V - v0);
+    const float *cg = c + (long long)v0 * C;
+    for (int e = tid; e < 64 * ld; e += 256) cb[e] = 0;
+    __syncthreads();
+    const float invC = 1.0f / (float)C;
+    for (int e = tid; e < nv * C; e += 256) {
+        int v = (int)(((float)e + 0.5f) * invC);
+        int k = e - v * C;
+        cb[v * ld + k] = f2bf(cg[e]);
+    }
+    __syncthreads();
+
+    const int KB = Cp / 16;
+    const int rt0 = (s0 * UP) / 16 + blockIdx.y * 16 + wave * 4;
+    const int kq = lane >> 4;
+    f4 acc[4][4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < KB; ++kb) {
+        s4 a[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = Bsw16[((long long)(rt0 + mt) * KB + kb) * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const s4 b = *reinterpret_cast<const s4 *>(cb + (nt * 16 + (lane & 15)) * ld + kb * 16 + 4 * kq);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma16x16x16bf16(a[mt], b, acc[nt][mt]);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int v = v0 + nt * 16 + (lane & 15);
+        if (v >= V) continue;
+        const long long vp = pad_index(v, ny, nz);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = blockIdx.y * 256 + wave * 64 + mt * 16 + 4 * kq;
+            const int p = row / UP, u0 = row % UP;
+            if (p < np) *reinterpret_cast<f4 *>(M + (long long)p * vol_pad * UP + vp * UP + u0) = acc[nt][mt];
+        }
+    }
+}
+
+template <int UP>
+static hipError_t map_bf16_t(const Dims &d, const float *c, const uint16_t *Bsw16, int s0, int np, float *M,
+                             hipStream_t st)
+{
+    const int V = d.nx * d.ny * d.nz;
+    const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
+    dim3 grid((V + 63) / 64, (np * UP + 255) / 256);
+    size_t lds = (size_t)64 * (d.Cp + 4) * sizeof(short);
+    hipLaunchKernelGGL(k_map_bf16<UP>, grid, dim3(256), lds, st, c, reinterpret_cast<const s4 *>(Bsw16), V, d.C,
+                       d.Cp, d.ny, d.nz, s0, np, vol_pad, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bsw16, int s0, int np, float *M,
+                           hipStream_t st)
+{
+    if ((s0 * d.Up) % 16) return hipErrorInvalidValue;
+    switch (d.Up) {
+    case 4: return map_bf16_t<4>(d, c, Bsw16, s0, np, M, st);
+    case 8: return map_bf16_t<8>(d, c, Bsw16, s0, np, M, st);
+    case 16: return map_bf16_t<16>(d, c, Bsw16, s0, np, M, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -146,9 +245,14 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
                                                int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
                                                float step, long long vol_pad, float *__restrict__ I)
 {
-    const int p = blockIdx.z, s = s0 + p;
-    const int j = blockIdx.y * 16 + (threadIdx.x & 15);
-    const int k = blockIdx.x * 16 + (threadIdx.x >> 4);
+    // tile: projection-major, then 16x16 ray tiles (dispatch order; an
+    // XCD-contiguous remap measured slower here)
+    const int ntj = (nj + 15) / 16, ntk = (nk + 15) / 16;
+    const int lb = blockIdx.x;
+    const int p = lb / (ntj * ntk), s = s0 + p;
+    const int tj = (lb / ntk) % ntj, tk = lb % ntk;
+    const int j = tj * 16 + (threadIdx.x & 15);
+    const int k = tk * 16 + (threadIdx.x >> 4);
     if (j >= nj || k >= nk) return;
     const ProjFrame &f = frames[s];
     const double n3[3] = {(double)nx, (double)ny, (double)nz};
@@ -215,7 +319,7 @@ static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M
                           hipStream_t st)
 {
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
-    dim3 grid((d.nk + 15) / 16, (d.nj + 15) / 16, np);
+    dim3 grid(((d.nk + 15) / 16) * ((d.nj + 15) / 16) * np);
     hipLaunchKernelGGL(k_march<UP>, grid, dim3(256), 0, st, M, frames, s0, d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg,
                        d.U, d.step, vol_pad, I);
     return hipGetLastError();
@@ -331,9 +435,9 @@ hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *dat
 // backproject: block = brick of 4 (x) x 8 (y) x 8 (z) voxels; wave w owns the
 // x-slice w (64 voxels = 4 column tiles of 16).  Loops over all projections.
 // ---------------------------------------------------------------------------
-template <int UP, int MT>
+template <int UP, int MT, bool BF16>
 __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ yf, const ProjFrame *__restrict__ frames,
-                                                     const float *__restrict__ Bu, int S, int nx, int ny, int nz,
+                                                     const float *__restrict__ Bu, const s4 *__restrict__ BuT16, int S, int nx, int ny, int nz,
                                                      int nj, int nk, int C, int Cp, float step,
                                                      float *__restrict__ g, float beta, const float *__restrict__ c,
                                                      double *__restrict__ partials)
@@ -342,7 +446,7 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
     __shared__ double ws[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nbx = (nx + 3) / 4, nby = (ny + 7) / 8;
-    const int bid = blockIdx.x;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
     const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
     const int ix = bx * 4 + wave, iy = by * 8 + (lane >> 3), iz = bz * 8 + (lane & 7);
     const bool valid = ix < nx && iy < ny && iz < nz;
@@ -423,17 +527,36 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
         for (int u = 0; u < UP; ++u) Qw[lane * (UP + 1) + u] = q[u];
         __syncthreads();
         // g tile += B_s^T (coefficients x u) * Q^T (u x voxels)
-        const float *Bs = Bu + (long long)s * UP * Cp;
+        if constexpr (BF16) {
+            // K = 16 (u padded with zeros): A from BuT16[s][coefficient][u], B = Q rounded to bf16
+            s4 av[MT];
 #pragma unroll
-        for (int ks = 0; ks < UP / 4; ++ks) {
-            float av[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) av[mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+            for (int mt = 0; mt < MT; ++mt) av[mt] = BuT16[((long long)s * Cp + mt * 16 + (lane & 15)) * 4 + (lane >> 4)];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                float bv = Qw[(nt * 16 + (lane & 15)) * (UP + 1) + ks * 4 + (lane >> 4)];
+                const float *qv = Qw + (nt * 16 + (lane & 15)) * (UP + 1);
+                const int u0 = 4 * (lane >> 4);
+                s4 bv;
+                bv.x = u0 + 0 < UP ? f2bf(qv[min(u0 + 0, UP - 1)]) : (short)0;
+                bv.y = u0 + 1 < UP ? f2bf(qv[min(u0 + 1, UP - 1)]) : (short)0;
+                bv.z = u0 + 2 < UP ? f2bf(qv[min(u0 + 2, UP - 1)]) : (short)0;
+                bv.w = u0 + 3 < UP ? f2bf(qv[min(u0 + 3, UP - 1)]) : (short)0;
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(av[mt], bv, acc[mt][nt]);
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x16bf16(av[mt], bv, acc[mt][nt]);
+            }
+        } else {
+            const float *Bs = Bu + (long long)s * UP * Cp;
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks) {
+                float av[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) av[mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    float bv = Qw[(nt * 16 + (lane & 15)) * (UP + 1) + ks * 4 + (lane >> 4)];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(av[mt], bv, acc[mt][nt]);
+                }
             }
         }
         __syncthreads();
@@ -474,38 +597,43 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
 int backproject_blocks(const Dims &d) { return ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
 
 template <int UP, int MT>
-static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu, float *g,
-                       float beta, const float *c, double *partials, hipStream_t st)
+static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu, const uint16_t *BuT16,
+                       int bf16, float *g, float beta, const float *c, double *partials, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_backproject<UP, MT>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames, Bu, d.S,
-                       d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    const s4 *bt = reinterpret_cast<const s4 *>(BuT16);
+    if (bf16)
+        hipLaunchKernelGGL((k_backproject<UP, MT, true>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames, Bu,
+                           bt, d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    else
+        hipLaunchKernelGGL((k_backproject<UP, MT, false>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames,
+                           Bu, bt, d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
     return hipGetLastError();
 }
 
 template <int UP>
-static hipError_t bp_mt(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu, float *g,
-                        float beta, const float *c, double *partials, hipStream_t st)
+static hipError_t bp_mt(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu,
+                        const uint16_t *BuT16, int bf16, float *g, float beta, const float *c, double *partials,
+                        hipStream_t st)
 {
     switch (d.Cp / 16) {
-    case 1: return bp_t<UP, 1>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 2: return bp_t<UP, 2>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 3: return bp_t<UP, 3>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 4: return bp_t<UP, 4>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 5: return bp_t<UP, 5>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 6: return bp_t<UP, 6>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 1: return bp_t<UP, 1>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 2: return bp_t<UP, 2>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 3: return bp_t<UP, 3>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 4: return bp_t<UP, 4>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 5: return bp_t<UP, 5>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 6: return bp_t<UP, 6>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu,
-                              const uint16_t *, int bf16, float *g, float beta, const float *c, double *partials,
+                              const uint16_t *BuT16, int bf16, float *g, float beta, const float *c, double *partials,
                               hipStream_t st)
 {
-    if (bf16) return hipErrorNotSupported;
     switch (d.Up) {
-    case 4: return bp_mt<4>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 8: return bp_mt<8>(d, frames, yf, Bu, g, beta, c, partials, st);
-    case 16: return bp_mt<16>(d, frames, yf, Bu, g, beta, c, partials, st);
+    case 4: return bp_mt<4>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 8: return bp_mt<8>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
+    case 16: return bp_mt<16>(d, frames, yf, Bu, BuT16, bf16, g, beta, c, partials, st);
     default: return hipErrorInvalidValue;
     }
 }

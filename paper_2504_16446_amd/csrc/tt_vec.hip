@@ -47,30 +47,49 @@ __device__ void block_sums(double (&acc)[NV], int nv, double *partials, int stri
 }
 
 // d = sum_a coef[a] b_a over masked a;  partials: d . b_a (a < nb) and d . d (index kMaxBasis).
+// float4 body over n / 4 elements, scalar tail.
 __global__ __launch_bounds__(256) void k_combine(VecList b, int nb, const double *__restrict__ coef,
                                                  const int *__restrict__ mask, long long n, float *__restrict__ d,
                                                  double *__restrict__ partials)
 {
     double acc[kMaxBasis + 1];
-#pragma unroll
-    for (int a = 0; a <= kMaxBasis; ++a) acc[a] = 0.0;
     float cf[kMaxBasis];
     bool mk[kMaxBasis];
+#pragma unroll
+    for (int a = 0; a <= kMaxBasis; ++a) acc[a] = 0.0;
 #pragma unroll
     for (int a = 0; a < kMaxBasis; ++a) {
         mk[a] = a < nb && mask[a];
         cf[a] = mk[a] ? (float)coef[a] : 0.0f;
     }
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n4; e += stride) {
+        f4 bv[kMaxBasis];
+        f4 dv = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < kMaxBasis; ++a) {
+            bv[a] = f4{0.f, 0.f, 0.f, 0.f};
+            if (mk[a]) {
+                bv[a] = reinterpret_cast<const f4 *>(b.p[a])[e];
+                dv += cf[a] * bv[a];
+            }
+        }
+        reinterpret_cast<f4 *>(d)[e] = dv;
+#pragma unroll
+        for (int a = 0; a < kMaxBasis; ++a)
+            if (mk[a])
+                acc[a] += (double)dv.x * bv[a].x + (double)dv.y * bv[a].y + (double)dv.z * bv[a].z +
+                          (double)dv.w * bv[a].w;
+        acc[kMaxBasis] += (double)dv.x * dv.x + (double)dv.y * dv.y + (double)dv.z * dv.z + (double)dv.w * dv.w;
+    }
+    for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
         float bv[kMaxBasis];
         float dv = 0.0f;
 #pragma unroll
         for (int a = 0; a < kMaxBasis; ++a) {
-            bv[a] = 0.0f;
-            if (mk[a]) {
-                bv[a] = b.p[a][e];
-                dv = fmaf(cf[a], bv[a], dv);
-            }
+            bv[a] = mk[a] ? b.p[a][e] : 0.0f;
+            dv = fmaf(cf[a], bv[a], dv);
         }
         d[e] = dv;
 #pragma unroll
@@ -80,10 +99,12 @@ __global__ __launch_bounds__(256) void k_combine(VecList b, int nb, const double
     block_sums<kMaxBasis + 1>(acc, kMaxBasis + 1, partials, kMaxBasis + 1);
 }
 
-// partials: x . b_a for masked a < nb.
+// partials: x . b_a for masked a < nb.  If ycand is set, also writes
+// y[cand] = x - b[gold] (the new curvature vector, in the same pass).
 __global__ __launch_bounds__(256) void k_multidot(const float *__restrict__ x, VecList b, int nb,
                                                   const int *__restrict__ mask, long long n,
-                                                  double *__restrict__ partials)
+                                                  double *__restrict__ partials, VecList ys,
+                                                  const int *__restrict__ ist, int gold)
 {
     double acc[kMaxBasis + 1];
     bool mk[kMaxBasis + 1];
@@ -92,11 +113,26 @@ __global__ __launch_bounds__(256) void k_multidot(const float *__restrict__ x, V
         acc[a] = 0.0;
         mk[a] = a < nb && mask[a];
     }
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
-        double xv = x[e];
+    float *yc = ist ? const_cast<float *>(ys.p[ist[kCand]]) : nullptr;
+    const float *go = ist ? b.p[gold] : nullptr;
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n4; e += stride) {
+        const f4 xv = reinterpret_cast<const f4 *>(x)[e];
+#pragma unroll
+        for (int a = 0; a <= kMaxBasis; ++a)
+            if (mk[a]) {
+                const f4 bv = reinterpret_cast<const f4 *>(b.p[a])[e];
+                acc[a] += (double)xv.x * bv.x + (double)xv.y * bv.y + (double)xv.z * bv.z + (double)xv.w * bv.w;
+            }
+        if (yc) reinterpret_cast<f4 *>(yc)[e] = xv - reinterpret_cast<const f4 *>(go)[e];
+    }
+    for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
+        const double xv = x[e];
 #pragma unroll
         for (int a = 0; a <= kMaxBasis; ++a)
             if (mk[a]) acc[a] += xv * (double)b.p[a][e];
+        if (yc) yc[e] = x[e] - go[e];
     }
     block_sums<kMaxBasis + 1>(acc, nb, partials, kMaxBasis + 1);
 }
@@ -133,8 +169,15 @@ __global__ __launch_bounds__(256) void k_update_c(float *__restrict__ c, const f
 {
     const float alpha = (float)st[kAlpha];
     float *sc = const_cast<float *>(s.p[ist[kCand]]);
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
-        float ad = alpha * d[e];
+    const long long n4 = n >> 2;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n4; e += stride) {
+        const f4 ad = alpha * reinterpret_cast<const f4 *>(d)[e];
+        reinterpret_cast<f4 *>(c)[e] += ad;
+        reinterpret_cast<f4 *>(sc)[e] = ad;
+    }
+    for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
+        const float ad = alpha * d[e];
         c[e] += ad;
         sc[e] = ad;
     }
@@ -363,9 +406,12 @@ hipError_t lbfgs_combine(const float *const *basis, int nb, const double *coef, 
 }
 
 hipError_t lbfgs_multidot(const float *x, const float *const *vecs, int nv, const int *mask, long long n,
-                          double *partials, double *out, hipStream_t s)
+                          double *partials, double *out, hipStream_t s, const float *const *y_slots, int ns,
+                          const int *ist, int gold)
 {
-    hipLaunchKernelGGL(k_multidot, dim3(kBlocks), dim3(256), 0, s, x, make_list(vecs, nv), nv, mask, n, partials);
+    VecList ys = y_slots ? make_list(y_slots, ns) : VecList{};
+    hipLaunchKernelGGL(k_multidot, dim3(kBlocks), dim3(256), 0, s, x, make_list(vecs, nv), nv, mask, n, partials, ys,
+                       y_slots ? ist : nullptr, gold);
     hipLaunchKernelGGL(k_sum_columns, dim3(nv), dim3(256), 0, s, partials, kBlocks, kMaxBasis + 1, out);
     return hipGetLastError();
 }

@@ -166,3 +166,26 @@ def test_ray_and_voxel_subsets_match_full():
     xyz[:3] = [[0, 0, 0], [g.n[0] - 1, g.n[1] - 1, g.n[2] - 1], [0, g.n[1] - 1, 0]]
     got = oracle.adjoint_voxels(g, y, xyz)
     assert np.abs(got - G[xyz[:, 0], xyz[:, 1], xyz[:, 2]]).max() < 1e-12 * np.abs(G).max()
+
+
+def test_segment_first_adjoint_equals_adjoint():
+    # sum_s B_s^T (P_s^T fold(y_s)) equals the adjoint computed ray by ray
+    for g in (small(ell_max=4), small(ell_max=8, n_seg=16), tiny(offsets=True, step=0.8)):
+        y = np.random.default_rng(31).standard_normal(g.data_shape)
+        ref = oracle.adjoint(g, y)
+        got = oracle.adjoint_segment_first(g, y)
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    # without antipodal folding (half-circle segments)
+    g = oracle.Geometry((7, 8, 9), 2, [0.3, 1.1], [0.0, 0.5], 9, 10, 6, synth.lab_frame(), seg_span=np.pi)
+    assert oracle.unique_segments(g) == 6
+    y = np.random.default_rng(32).standard_normal(g.data_shape)
+    assert np.abs(oracle.adjoint_segment_first(g, y) - oracle.adjoint(g, y)).max() < 1e-12 * np.abs(oracle.adjoint(g, y)).max()
+
+
+def test_bf16_rounding_helper():
+    x = np.array([1.0, 1.00390625, 1.005859375, -3.1415926, 1e-3, 65504.0])
+    r = oracle.bf16(x)
+    # 8 significant bits: 1 + 2^-8 is a tie between 1 and 1 + 2^-7 and rounds to even (1.0)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0078125
+    assert abs(r[3] + 3.140625) < 1e-12
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
