@@ -170,6 +170,50 @@ int tt_lbfgs_query(tt_lbfgs *st, double *out4);
 int tt_lbfgs_run(tt_lbfgs *st, int max_iter, double rel_tol, double *hist, int *iters_out);
 
 /* ------------------------------------------------------------------------ */
+/* Learned warm start.  The paper's outlook (section 4) names simulated data */
+/* for training machine-learning models; here a small 3-D convolutional      */
+/* network maps the normalised backprojection A^T I to initial coefficients. */
+/* Layers: y[v, co] = b[co] + sum_{d in {0,1,2}^3} sum_ci x[v + d - 1, ci]     */
+/* w[d, ci, co], zero padding, tap index d = (dx*3 + dy)*3 + dz.  Layout is   */
+/* channels-last x[n][X][Y][Z][c]; activations bf16 (uint16 bit patterns),    */
+/* accumulation fp32 on bf16 MFMA.  ci, co must be 32 or 64.  All pointers    */
+/* are device pointers owned by the caller; work is enqueued on `stream`.     */
+/* ------------------------------------------------------------------------ */
+enum { TT_CONV_RELU_BF16 = 0, TT_CONV_BIAS_F32 = 1, TT_CONV_MASK_BF16 = 2 };
+
+/* bf16 elements of one MFMA-ordered weight copy for (ci, co). */
+int64_t tt_conv3d_weight_elems(int ci, int co);
+/* From fp32 masters w[27][ci][co]: wf (forward operand order) and wd (the
+ * input-gradient operator w'[d][co][ci] = w[26 - d][ci][co], same order). */
+int tt_conv3d_swizzle(const float *w, int ci, int co, uint16_t *wf, uint16_t *wd, void *stream);
+/* y = conv(x, wf) with epilogue TT_CONV_RELU_BF16 (relu(. + bias), bf16 y),
+ * TT_CONV_BIAS_F32 (. + bias, float y) or TT_CONV_MASK_BF16 (zero where
+ * mask <= 0, bf16 y; with wd this is the input gradient through a ReLU whose
+ * output is mask).  mask has co channels; bias may be NULL only for MASK. */
+int tt_conv3d(int epilogue, int ci, int co, const uint16_t *x, const uint16_t *w_swizzled, const float *bias,
+              const uint16_t *mask, void *y, int n, int X, int Y, int Z, void *stream);
+/* Weight (and bias, if gb != NULL) gradients: gw[27][ci][co] =
+ * sum_v x[v + d - 1, ci] gy[v, co], gb[co] = sum_v gy[v, co].  Deterministic
+ * (split over voxels, partials summed in a fixed order).  work: float device
+ * buffer of tt_conv3d_wgrad_work_bytes bytes. */
+size_t tt_conv3d_wgrad_work_bytes(int ci, int co, int n, int X, int Y, int Z);
+int tt_conv3d_wgrad(int ci, int co, const uint16_t *x, const uint16_t *gy, int n, int X, int Y, int Z, float *work,
+                    size_t work_bytes, float *gw, float *gb, void *stream);
+/* One Adam step (Kingma & Ba) on n fp32 parameters, step count t >= 1. */
+int tt_adam(float *w, const float *g, float *m, float *v, int64_t n, int t, float lr, float beta1, float beta2,
+            float eps, void *stream);
+/* Mean-squared-error gradient: gy[v][c] = scale (y[v][c] - t[v][c]) for
+ * c < creal (0 for creal <= c < cpad) in bf16 (gy may be NULL), and
+ * loss[0] = sum (y - t)^2 in float64.  y is [nvox][cpad], t is
+ * [nvox][creal]; work holds >= 1024 doubles. */
+int tt_mse(const float *y, const float *t, int64_t nvox, int cpad, int creal, float scale, uint16_t *gy,
+           double *loss, double *work, int64_t work_len, void *stream);
+/* out[v][c] = bf16(scale[c] (x[v][c] - shift[c])) for c < cin, 0 up to cpad
+ * (shift, scale may be NULL). */
+int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, const float *shift, const float *scale,
+                 uint16_t *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Optional kernel timing: when enabled, every kernel launch of the context  */
 /* is bracketed by HIP events on the context's stream, per kernel class.     */
 /* ------------------------------------------------------------------------ */

@@ -65,6 +65,16 @@ _SIGS = [
     ("tt_lbfgs_run", C.c_int, [_vp, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     ("tt_timing_enable", C.c_int, [_vp, C.c_int]),
     ("tt_timing_read", C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("tt_conv3d_weight_elems", C.c_int64, [C.c_int, C.c_int]),
+    ("tt_conv3d_swizzle", C.c_int, [_fp, C.c_int, C.c_int, _vp, _vp, _vp]),
+    ("tt_conv3d", C.c_int, [C.c_int, C.c_int, C.c_int, _vp, _vp, _fp, _vp, _vp, C.c_int, C.c_int, C.c_int,
+                            C.c_int, _vp]),
+    ("tt_conv3d_wgrad_work_bytes", C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("tt_conv3d_wgrad", C.c_int, [C.c_int, C.c_int, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _fp, C.c_size_t,
+                                  _fp, _fp, _vp]),
+    ("tt_adam", C.c_int, [_fp, _fp, _fp, _fp, C.c_int64, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    ("tt_mse", C.c_int, [_fp, _fp, C.c_int64, C.c_int, C.c_int, C.c_float, _vp, _dp, _dp, C.c_int64, _vp]),
+    ("tt_pack_bf16", C.c_int, [_fp, C.c_int64, C.c_int, C.c_int, _fp, _fp, _vp, _vp]),
     ("tt_last_error", C.c_char_p, []),
     ("tt_error_string", C.c_char_p, [C.c_int]),
 ]

@@ -654,4 +654,83 @@ int tt_lbfgs_run(tt_lbfgs *st, int max_iter, double rel_tol, double *hist, int *
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// warm-start network layers
+// ---------------------------------------------------------------------------
+static bool net_channels_ok(int ci, int co) { return (ci == 32 || ci == 64) && (co == 32 || co == 64); }
+
+int64_t tt_conv3d_weight_elems(int ci, int co)
+{
+    if (!net_channels_ok(ci, co)) return fail(TT_EUNSUPPORTED, "channels must be 32 or 64");
+    return (int64_t)27 * ci * co;
+}
+
+int tt_conv3d_swizzle(const float *w, int ci, int co, uint16_t *wf, uint16_t *wd, void *stream)
+{
+    if (!w || !wf || !wd) return fail(TT_EINVAL, "null pointer");
+    if (!net_channels_ok(ci, co)) return fail(TT_EUNSUPPORTED, "channels must be 32 or 64");
+    TT_HIP(net_swizzle(w, ci, co, wf, wd, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_conv3d(int epi, int ci, int co, const uint16_t *x, const uint16_t *wsw, const float *bias, const uint16_t *mask,
+              void *y, int n, int X, int Y, int Z, void *stream)
+{
+    if (!x || !wsw || !y) return fail(TT_EINVAL, "null pointer");
+    if (epi < 0 || epi > 2) return fail(TT_EINVAL, "bad epilogue");
+    if (epi != TT_CONV_MASK_BF16 && !bias) return fail(TT_EINVAL, "bias is null");
+    if (epi == TT_CONV_MASK_BF16 && !mask) return fail(TT_EINVAL, "mask is null");
+    if (!net_channels_ok(ci, co)) return fail(TT_EUNSUPPORTED, "channels must be 32 or 64");
+    if (n < 1 || X < 1 || Y < 1 || Z < 1) return fail(TT_ESHAPE, "empty volume");
+    TT_HIP(net_conv(epi, ci, co, x, wsw, bias, mask, y, n, X, Y, Z, (hipStream_t)stream));
+    return TT_OK;
+}
+
+size_t tt_conv3d_wgrad_work_bytes(int ci, int co, int n, int X, int Y, int Z)
+{
+    if (!net_channels_ok(ci, co) || n < 1 || X < 1 || Y < 1 || Z < 1) return 0;
+    return net_wgrad_work_bytes(ci, co, n, X, Y, Z);
+}
+
+int tt_conv3d_wgrad(int ci, int co, const uint16_t *x, const uint16_t *gy, int n, int X, int Y, int Z, float *work,
+                    size_t work_bytes, float *gw, float *gb, void *stream)
+{
+    if (!x || !gy || !work || !gw) return fail(TT_EINVAL, "null pointer");
+    if (!net_channels_ok(ci, co)) return fail(TT_EUNSUPPORTED, "channels must be 32 or 64");
+    if (n < 1 || X < 1 || Y < 1 || Z < 1) return fail(TT_ESHAPE, "empty volume");
+    if (work_bytes < net_wgrad_work_bytes(ci, co, n, X, Y, Z)) return fail(TT_EINVAL, "work buffer too small");
+    TT_HIP(net_wgrad(ci, co, x, gy, n, X, Y, Z, work, gw, gb, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_adam(float *w, const float *g, float *m, float *v, int64_t n, int t, float lr, float b1, float b2, float eps,
+            void *stream)
+{
+    if (!w || !g || !m || !v) return fail(TT_EINVAL, "null pointer");
+    if (n < 0 || t < 1) return fail(TT_EINVAL, "n >= 0 and t >= 1 required");
+    if (n == 0) return TT_OK;
+    TT_HIP(net_adam(w, g, m, v, n, t, lr, b1, b2, eps, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_mse(const float *y, const float *t, int64_t nvox, int cpad, int creal, float scale, uint16_t *gy, double *loss,
+           double *work, int64_t work_len, void *stream)
+{
+    if (!y || !t || !loss || !work) return fail(TT_EINVAL, "null pointer");
+    if (nvox < 1 || creal < 1 || cpad < creal) return fail(TT_ESHAPE, "bad sizes");
+    if (work_len < 1024) return fail(TT_EINVAL, "work must hold 1024 doubles");
+    TT_HIP(net_mse(y, t, nvox, cpad, creal, scale, gy, work, 1024, loss, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, const float *shift, const float *scale,
+                 uint16_t *out, void *stream)
+{
+    if (!x || !out) return fail(TT_EINVAL, "null pointer");
+    if (nvox < 0 || cin < 1 || cpad < cin) return fail(TT_ESHAPE, "bad sizes");
+    if (nvox == 0) return TT_OK;
+    TT_HIP(net_pack(x, nvox, cin, cpad, shift, scale, out, (hipStream_t)stream));
+    return TT_OK;
+}
+
 }  // extern "C"

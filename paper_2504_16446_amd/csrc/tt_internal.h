@@ -77,4 +77,20 @@ int backproject_blocks(const Dims &d);
 hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,
                                int accumulate, hipStream_t st);
 
+// Warm-start network layers (tt_net.hip).  epi: 0 bias + ReLU -> bf16,
+// 1 bias -> fp32, 2 zero where mask <= 0 -> bf16 (dgrad with the ReLU mask).
+hipError_t net_conv(int epi, int ci, int co, const uint16_t *x, const void *wsw, const float *bias,
+                    const uint16_t *mask, void *y, int N, int X, int Y, int Z, hipStream_t st);
+int net_wgrad_chunks(int N, int X, int Y, int Z);
+size_t net_wgrad_work_bytes(int ci, int co, int N, int X, int Y, int Z);
+hipError_t net_wgrad(int ci, int co, const uint16_t *x, const uint16_t *gy, int N, int X, int Y, int Z, float *work,
+                     float *gw, float *gb, hipStream_t st);
+hipError_t net_swizzle(const float *w, int ci, int co, void *wf, void *wd, hipStream_t st);
+hipError_t net_adam(float *w, const float *g, float *m, float *v, long long n, int t, float lr, float b1, float b2,
+                    float eps, hipStream_t st);
+hipError_t net_mse(const float *y, const float *t, long long nvox, int cpad, int creal, float scale, uint16_t *gy,
+                   double *partials, int nblocks, double *loss, hipStream_t st);
+hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, const float *shift, const float *scale,
+                    uint16_t *out, hipStream_t st);
+
 }  // namespace tt
