@@ -213,6 +213,21 @@ int tt_mse(const float *y, const float *t, int64_t nvox, int cpad, int creal, fl
 int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, const float *shift, const float *scale,
                  uint16_t *out, void *stream);
 
+/* Patchwise inference on T^3 tiles at per-axis origins ox[ntx], oy[nty],
+ * oz[ntz] (device int arrays; tile t = (ix nty + iy) ntz + iz).  Origins must
+ * satisfy o + T <= volume size, tiles covering the whole volume.
+ * tt_tile_gather: tiles t0 .. t0+nt-1 of vol[X][Y][Z][cv] (channels < cin),
+ * standardised and packed to bf16 out[nt][T][T][T][cpad].
+ * tt_tile_blend: out[X][Y][Z][cout] = sum_t w_t y_t / sum_t w_t on channels
+ * < creal (0 above), y = all tiles' outputs [ntiles][T][T][T][cy] float,
+ * w_t the product of per-axis linear ramps over `ramp` voxels on sides that
+ * overlap a neighbouring tile. */
+int tt_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
+                   const int *oy, int nty, const int *oz, int ntz, int T, const float *shift, const float *scale,
+                   int t0, int nt, uint16_t *out, void *stream);
+int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const int *ox, int ntx, const int *oy,
+                  int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Optional kernel timing: when enabled, every kernel launch of the context  */
 /* is bracketed by HIP events on the context's stream, per kernel class.     */

@@ -75,6 +75,10 @@ _SIGS = [
     ("tt_adam", C.c_int, [_fp, _fp, _fp, _fp, C.c_int64, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     ("tt_mse", C.c_int, [_fp, _fp, C.c_int64, C.c_int, C.c_int, C.c_float, _vp, _dp, _dp, C.c_int64, _vp]),
     ("tt_pack_bf16", C.c_int, [_fp, C.c_int64, C.c_int, C.c_int, _fp, _fp, _vp, _vp]),
+    ("tt_tile_gather", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp,
+                                 C.c_int, _vp, C.c_int, C.c_int, _fp, _fp, C.c_int, C.c_int, _vp, _vp]),
+    ("tt_tile_blend", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp,
+                                C.c_int, C.c_int, C.c_int, C.c_int, _fp, _vp]),
     ("tt_last_error", C.c_char_p, []),
     ("tt_error_string", C.c_char_p, [C.c_int]),
 ]

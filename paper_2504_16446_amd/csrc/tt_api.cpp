@@ -267,12 +267,21 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
             for (int u = 0; u < d.Up; ++u) but16[((size_t)s * d.Cp + i) * 16 + u] = to_bf16(bu[((size_t)s * d.Up + u) * d.Cp + i]);
     c->vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     const size_t per_proj = (size_t)c->vol_pad * d.Up * sizeof(float);
+    // Projections per forward batch: the map reads c once per batch, so the
+    // batch should fill the map kernel's 256-row tiles (256 / Up projections)
+    // and be as large as memory allows; default budget 1/8 of the free device
+    // memory, clamped to [1, 24] GiB.
+    size_t free_b = 0, total_b = 0;
     size_t budget = (size_t)1 << 30;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+        budget = std::min<size_t>((size_t)24 << 30, std::max<size_t>((size_t)1 << 30, free_b / 8));
     if (const char *e = std::getenv("TT_FORWARD_BATCH_BYTES")) budget = (size_t)std::strtoull(e, nullptr, 10);
     c->pb = (int)std::max<size_t>(1, std::min<size_t>((size_t)S, budget / per_proj));
-    // batches start on a 16-row tile of (projection, segment) rows
-    const int align = 16 / d.Up;
-    if (c->pb < S) c->pb = std::max(align, c->pb / align * align);
+    const int align = 16 / d.Up, full = 256 / d.Up;
+    if (c->pb < S) {
+        if (c->pb >= full) c->pb = c->pb / full * full;
+        else c->pb = std::max(align, c->pb / align * align);
+    }
     // MFMA-ordered copy of Bu: tile rt, k-step ks, lane l -> Bu[16 rt + l % 16][4 ks + l / 16]
     std::vector<float> bsw(bu.size(), 0.0f);
     const int KS = d.Cp / 4;
@@ -730,6 +739,31 @@ int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, const float *s
     if (nvox < 0 || cin < 1 || cpad < cin) return fail(TT_ESHAPE, "bad sizes");
     if (nvox == 0) return TT_OK;
     TT_HIP(net_pack(x, nvox, cin, cpad, shift, scale, out, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
+                   const int *oy, int nty, const int *oz, int ntz, int T, const float *shift, const float *scale,
+                   int t0, int nt, uint16_t *out, void *stream)
+{
+    if (!vol || !ox || !oy || !oz || !out) return fail(TT_EINVAL, "null pointer");
+    if (X < 1 || Y < 1 || Z < 1 || cin < 1 || cv < cin || cpad < cin || T < 1 || ntx < 1 || nty < 1 || ntz < 1)
+        return fail(TT_ESHAPE, "bad sizes");
+    if (t0 < 0 || nt < 0 || t0 + nt > ntx * nty * ntz) return fail(TT_EINVAL, "tile range out of bounds");
+    if (nt == 0) return TT_OK;
+    TT_HIP(net_tile_gather(vol, X, Y, Z, cv, cin, cpad, ox, ntx, oy, nty, oz, ntz, T, shift, scale, t0, nt, out,
+                           (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const int *ox, int ntx, const int *oy,
+                  int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, void *stream)
+{
+    if (!y || !ox || !oy || !oz || !out) return fail(TT_EINVAL, "null pointer");
+    if (X < 1 || Y < 1 || Z < 1 || creal < 1 || cy < creal || cout < creal || T < 1 || ramp < 1 || ntx < 1 ||
+        nty < 1 || ntz < 1)
+        return fail(TT_ESHAPE, "bad sizes");
+    TT_HIP(net_tile_blend(y, cy, creal, X, Y, Z, ox, ntx, oy, nty, oz, ntz, T, ramp, cout, out, (hipStream_t)stream));
     return TT_OK;
 }
 

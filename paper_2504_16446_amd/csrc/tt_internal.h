@@ -92,5 +92,10 @@ hipError_t net_mse(const float *y, const float *t, long long nvox, int cpad, int
                    double *partials, int nblocks, double *loss, hipStream_t st);
 hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, const float *shift, const float *scale,
                     uint16_t *out, hipStream_t st);
+hipError_t net_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
+                           const int *oy, int nty, const int *oz, int ntz, int T, const float *shift,
+                           const float *scale, int t0, int nt, uint16_t *out, hipStream_t st);
+hipError_t net_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const int *ox, int ntx, const int *oy,
+                          int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, hipStream_t st);
 
 }  // namespace tt

@@ -355,6 +355,84 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, long 
     }
 }
 
+// Patchwise inference.  Tiles of T^3 voxels at per-axis origins ox[], oy[], oz[]
+// (tile t = (i nx_t + j) ny_t... in x-major order).
+// gather: out[t][T^3][cpad] = bf16(scale[c] (vol[o_t + u][c] - shift[c])) for c < cin.
+__global__ __launch_bounds__(256) void k_tile_gather(const float *__restrict__ vol, int X, int Y, int Z, int cv, int cin,
+                                                     int cpad, const int *__restrict__ ox, int ntx,
+                                                     const int *__restrict__ oy, int nty, const int *__restrict__ oz,
+                                                     int ntz, int T, const float *__restrict__ shift,
+                                                     const float *__restrict__ scale, int t0, int nt,
+                                                     u16 *__restrict__ out)
+{
+    const long long per = (long long)T * T * T * cpad;
+    const long long n = per * nt;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const int t = t0 + (int)(e / per);
+        long long r = e % per;
+        const int c = (int)(r % cpad);
+        r /= cpad;
+        const int uz = (int)(r % T), uy = (int)((r / T) % T), ux = (int)(r / ((long long)T * T));
+        const int iz = t % ntz, iy = (t / ntz) % nty, ix = t / (ntz * nty);
+        const int gx = ox[ix] + ux, gy = oy[iy] + uy, gz = oz[iz] + uz;
+        float v = 0.0f;
+        if (c < cin && gx < X && gy < Y && gz < Z) {
+            v = vol[(((long long)gx * Y + gy) * Z + gz) * cv + c];
+            if (shift) v -= shift[c];
+            if (scale) v *= scale[c];
+        }
+        out[e] = f2bf(v);
+    }
+}
+
+// Separable blending weight of position u in a tile starting at o along an
+// axis of length n: a linear ramp over `ramp` voxels on sides that overlap
+// another tile, 1 on sides at the volume boundary.
+__device__ __forceinline__ float ramp_w(int u, int o, int T, int n, int ramp)
+{
+    float w = 1.0f;
+    if (o > 0) w = fminf(w, (u + 0.5f) / ramp);
+    if (o + T < n) w = fminf(w, (T - u - 0.5f) / ramp);
+    return w;
+}
+
+// blend: out[v][c] = sum_t w_t(v) y_t[v - o_t][c] / sum_t w_t(v) for c < creal,
+// 0 for creal <= c < cout.  One thread per (voxel, channel); fixed tile order.
+__global__ __launch_bounds__(256) void k_tile_blend(const float *__restrict__ y, int cy, int creal, int X, int Y, int Z,
+                                                    const int *__restrict__ ox, int ntx, const int *__restrict__ oy,
+                                                    int nty, const int *__restrict__ oz, int ntz, int T, int ramp,
+                                                    int cout, float *__restrict__ out)
+{
+    const long long n = (long long)X * Y * Z * cout;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const int c = (int)(e % cout);
+        const long long v = e / cout;
+        const int gz = (int)(v % Z), gy = (int)((v / Z) % Y), gx = (int)(v / ((long long)Y * Z));
+        float num = 0.0f, den = 0.0f;
+        if (c < creal) {
+            for (int ix = 0; ix < ntx; ++ix) {
+                const int ux = gx - ox[ix];
+                if (ux < 0 || ux >= T) continue;
+                const float wx = ramp_w(ux, ox[ix], T, X, ramp);
+                for (int iy = 0; iy < nty; ++iy) {
+                    const int uy = gy - oy[iy];
+                    if (uy < 0 || uy >= T) continue;
+                    const float wy = ramp_w(uy, oy[iy], T, Y, ramp);
+                    for (int iz = 0; iz < ntz; ++iz) {
+                        const int uz = gz - oz[iz];
+                        if (uz < 0 || uz >= T) continue;
+                        const float w = wx * wy * ramp_w(uz, oz[iz], T, Z, ramp);
+                        const long long t = ((long long)ix * nty + iy) * ntz + iz;
+                        num += w * y[((t * T + ux) * T + uy) * (long long)T * cy + (long long)uz * cy + c];
+                        den += w;
+                    }
+                }
+            }
+        }
+        out[e] = den > 0.0f ? num / den : 0.0f;
+    }
+}
+
 int grid_for(long long n) { return (int)min((n + 255) / 256, 8192LL); }
 
 template <int CI, int CO, int EPI>
@@ -454,6 +532,25 @@ hipError_t net_mse(const float *y, const float *t, long long nvox, int cpad, int
 {
     hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, st, y, t, nvox, cpad, creal, scale, gy, partials);
     return launch_sum_partials(partials, nblocks, loss, 1.0, 0, st);
+}
+
+hipError_t net_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
+                           const int *oy, int nty, const int *oz, int ntz, int T, const float *shift,
+                           const float *scale, int t0, int nt, uint16_t *out, hipStream_t st)
+{
+    const long long n = (long long)T * T * T * cpad * nt;
+    hipLaunchKernelGGL(k_tile_gather, dim3(grid_for(n)), dim3(256), 0, st, vol, X, Y, Z, cv, cin, cpad, ox, ntx, oy, nty,
+                       oz, ntz, T, shift, scale, t0, nt, out);
+    return hipGetLastError();
+}
+
+hipError_t net_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const int *ox, int ntx, const int *oy,
+                          int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, hipStream_t st)
+{
+    const long long n = (long long)X * Y * Z * cout;
+    hipLaunchKernelGGL(k_tile_blend, dim3(grid_for(n)), dim3(256), 0, st, y, cy, creal, X, Y, Z, ox, ntx, oy, nty, oz,
+                       ntz, T, ramp, cout, out);
+    return hipGetLastError();
 }
 
 hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, const float *shift, const float *scale,

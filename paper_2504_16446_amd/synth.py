@@ -153,33 +153,45 @@ def twisted_fibre_field(w: Workload, seed: int | None = None):
     return direction, degree, density
 
 
-def multi_bundle_field(w: Workload, seed: int | None = None, background=0.1):
-    """One to three straight cylindrical fibre bundles inside a ball.
+def bundle_params(w: Workload, seed: int | None = None):
+    """Random parameters of the multi-bundle phantom.
 
-    Returns ``(bundles, background_density)`` where ``bundles`` is a list of
-    ``(direction[3], degree, mask[nx,ny,nz])`` and ``background_density`` is an
-    isotropic density (``background`` inside the ball, 0 outside).  Each bundle
-    has an axis uniform on the sphere through a point uniform in the ball of
-    radius 0.2 N, a radius uniform in [0.08 N, 0.2 N] and a degree of
-    orientation uniform in [0, 1]; masks are clipped to the ball.
+    Returns a list of ``(axis[3], centre[3], radius, degree)``, one per bundle
+    (1 to 3 bundles): axis uniform on the sphere, centre uniform in the ball of
+    radius 0.2 N, radius uniform in [0.08 N, 0.2 N], degree of orientation
+    uniform in [0, 1].
     """
     rng = np.random.default_rng(w.seed_phantom if seed is None else seed)
     N = float(max(w.n))
-    x = _centred_grid(w.n)
-    ball = np.linalg.norm(x, axis=-1) <= w.radius
     k = int(rng.integers(1, 4))
-    bundles = []
+    out = []
     for _ in range(k):
         axis = _unit(rng)
         u = _unit(rng)
         centre = u * (0.2 * N) * rng.uniform() ** (1.0 / 3.0)
         radius = rng.uniform(0.08 * N, 0.2 * N)
         degree = rng.uniform(0.0, 1.0)
+        out.append((axis, centre, float(radius), float(degree)))
+    return out
+
+
+def multi_bundle_field(w: Workload, seed: int | None = None, background=0.1):
+    """One to three straight cylindrical fibre bundles inside a ball.
+
+    Returns ``(bundles, background_density)`` where ``bundles`` is a list of
+    ``(direction[3], degree, mask[nx,ny,nz])`` and ``background_density`` is an
+    isotropic density (``background`` inside the ball, 0 outside).  Bundle
+    parameters as in ``bundle_params``; masks are clipped to the ball.
+    """
+    x = _centred_grid(w.n)
+    ball = np.linalg.norm(x, axis=-1) <= w.radius
+    bundles = []
+    for axis, centre, radius, degree in bundle_params(w, seed):
         rel = x - centre
         along = rel @ axis
         perp = rel - along[..., None] * axis
         mask = (np.linalg.norm(perp, axis=-1) <= radius) & ball
-        bundles.append((axis, float(degree), mask.astype(np.float64)))
+        bundles.append((axis, degree, mask.astype(np.float64)))
     return bundles, background * ball.astype(np.float64)
 
 
