@@ -113,6 +113,86 @@ def cpu_baseline(w, n_sample, c_np, y_np):
     }
 
 
+def warm_vs_plain_heldout(dev, n=4, plain_iters=30):
+    """Learned warm start vs zero start on held-out 48^3 phantoms: wall time to the
+    residual the zero start reaches after plain_iters iterations (medians)."""
+    import numpy as np
+    import torch
+    from paper_2504_16446_amd import synth, warmstart
+    from paper_2504_16446_amd.projector import LBFGS, Projector
+
+    if not os.path.exists(warmstart.DEFAULT_WEIGHTS):
+        return None
+    model = warmstart.load(warmstart.DEFAULT_WEIGHTS, dev)
+    w = synth.WORKLOADS["c4"]
+    P = Projector.from_workload(w, device=dev)
+    kap = warmstart.kappa(P, w.radius)
+    rows = []
+    for seed in 1_000_000 + np.arange(n):
+        c_true = warmstart.bundle_phantom(w, int(seed), dev)
+        data = P.forward(c_true)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(seed) + 100000)
+        data.add_(torch.randn(data.shape, generator=gen, device=dev), alpha=w.noise * float(data.abs().max()))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = torch.zeros(P.vol_shape, device=dev)
+        it_p, _, rel_p, s1 = warmstart.lbfgs_to(P, data, w.mu, c, 0.0, plain_iters, log_every=0)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        del s1
+        t0 = time.perf_counter()
+        c0, _, fb = warmstart.warm_start(model, P, data, kap=kap)
+        c = torch.zeros(P.vol_shape, device=dev)
+        it_w, _, rel_w, s2 = warmstart.lbfgs_to(P, data, w.mu, c, rel_p, 4 * plain_iters, log_every=0,
+                                                first_direction=c0)
+        torch.cuda.synchronize()
+        t_warm = time.perf_counter() - t0
+        del s2
+        rows.append((t_plain, it_p, t_warm, it_w, rel_p))
+    a = np.array(rows)
+    return {"workload": "c4 held-out phantoms (seeds 1e6..), 48^3, ell_max 6, 120 projections, 1% noise",
+            "phantoms": n, "target": f"zero-start residual after {plain_iters} iterations",
+            "plain_seconds_median": float(np.median(a[:, 0])), "plain_iterations": plain_iters,
+            "warm_seconds_median": float(np.median(a[:, 2])), "warm_iterations_median": float(np.median(a[:, 3])),
+            "speedup_median": float(np.median(a[:, 0] / a[:, 2])),
+            "note": "warm time includes the scale kappa, backprojection, inference and blending"}
+
+
+def precision_report(dev, n_rays=128, n_vox=16):
+    """Errors of the fp32 and bf16 map tiers against the float64 oracle on the
+    128^3 / ell_max 8 / 300-projection / 16-segment workload (sampled outputs)."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2504_16446_amd import phantom, synth
+    from paper_2504_16446_amd.projector import Projector
+
+    w = synth.WORKLOADS["c3"]
+    og = oracle.Geometry.from_workload(w)
+    rng = np.random.default_rng(5)
+    c = phantom.coefficients(w)
+    y = rng.standard_normal((w.n_proj, w.nj, w.nk, w.n_seg), dtype=np.float32)
+    sjk = np.stack([rng.integers(0, w.n_proj, n_rays), rng.integers(0, w.nj, n_rays),
+                    rng.integers(0, w.nk, n_rays)], 1)
+    xyz = np.stack([rng.integers(0, m, n_vox) for m in w.n], 1)
+    ref_f = oracle.project_rays(og, c, sjk)
+    ref_a = oracle.adjoint_voxels(og, y, xyz)
+    out = {"workload": "c3", "inputs": "phantom coefficients; Gaussian data",
+           "sampled": f"{n_rays} rays x {w.n_seg} segments, {n_vox} voxels x {w.n_coeff} coefficients"}
+    P = Projector.from_workload(w, device=dev)
+    ct, yt = torch.from_numpy(c).to(dev), torch.from_numpy(y).to(dev)
+    for tier in ("fp32", "bf16"):
+        P.set_precision(tier)
+        I = P.forward(ct)
+        g = P.adjoint(yt)
+        got_f = I[sjk[:, 0], sjk[:, 1], sjk[:, 2]].cpu().numpy().astype(np.float64)
+        got_a = g[xyz[:, 0], xyz[:, 1], xyz[:, 2]].cpu().numpy().astype(np.float64)
+        out[tier] = {"forward_rel_l2": float(np.linalg.norm(got_f - ref_f) / np.linalg.norm(ref_f)),
+                     "adjoint_rel_l2": float(np.linalg.norm(got_a - ref_a) / np.linalg.norm(ref_a))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,7 +201,11 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--ttr-iters", type=int, default=None,
                     help="plain L-BFGS iterations for time-to-residual (default: the workload's)")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="projections in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="projections in the CPU-oracle sample")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--ttr-c5", action="store_true",
+                    help="also run the 256^3 plain-vs-warm comparison to relative residual 1e-3 (minutes)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision report")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
@@ -216,15 +300,26 @@ def main():
     r = P.forward(c2) - data
     final_rel = float(r.double().norm() / data.double().norm())
     del solver2, r
-    ttr = {"plain": {"iterations": n_done, "seconds": ttr_s, "final_rel_residual": final_rel,
+    ttr = {"plain": {"workload": w.name, "iterations": n_done, "seconds": ttr_s, "final_rel_residual": final_rel,
                      "loss_first_last": [float(hist[0, 0]), float(hist[-1, 0])] if n_done else None},
            "warm_start": None}
-
+    del solver
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle sample ...", file=sys.stderr, flush=True)
-        y_np = data.cpu().numpy()
-        cpu = cpu_baseline(w, args.cpu_sample, c_true_np, y_np)
+        cpu = cpu_baseline(w, args.cpu_sample, c_true_np, data.cpu().numpy())
+    if not args.no_warm:
+        print("[bench] warm start vs plain ...", file=sys.stderr, flush=True)
+        ttr["warm_start"] = warm_vs_plain_heldout(dev)
+        if args.ttr_c5:
+            from paper_2504_16446_amd import warmstart
+            del P, data, c, c2
+            torch.cuda.empty_cache()
+            model = warmstart.load(warmstart.DEFAULT_WEIGHTS, dev)
+            ttr["warm_start_c5"] = warmstart.compare(model, synth.WORKLOADS["c5"], 1e-3, 1500)
+    print("[bench] precision report ...", file=sys.stderr, flush=True)
+    precision = None if args.no_precision else precision_report(dev)
 
     line = {
         "metric": "fwd+adj projector GB/s & % HBM roof; time-to-residual warm-start vs plain",
@@ -239,6 +334,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "time_to_residual": ttr,
+        "precision": precision,
     }
     print(json.dumps(line), flush=True)
 

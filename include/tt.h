@@ -159,6 +159,13 @@ int tt_lbfgs_init(tt_lbfgs *st, float *c_dev, const float *data_dev, const float
  * history update).  Asynchronous: no host synchronisation. */
 int tt_lbfgs_step(tt_lbfgs *st);
 
+/* One iteration along the caller's direction d_dev (coefficient layout)
+ * instead of the two-loop direction: exact line search along d, update, and
+ * the curvature pair (alpha d, g_new - g) enters the history.  Used to start
+ * from zero along a predicted solution (a warm start whose scale the line
+ * search chooses).  Asynchronous. */
+int tt_lbfgs_step_direction(tt_lbfgs *st, const float *d_dev);
+
 /* Synchronise and read the state: out4 = {loss, ||r||_2, ||I||_2,
  * accepted pairs}.  out4 may hold 4 doubles. */
 int tt_lbfgs_query(tt_lbfgs *st, double *out4);

@@ -61,6 +61,7 @@ _SIGS = [
     ("tt_lbfgs_destroy", None, [_vp]),
     ("tt_lbfgs_init", C.c_int, [_vp, _fp, _fp, _fp, C.c_double]),
     ("tt_lbfgs_step", C.c_int, [_vp]),
+    ("tt_lbfgs_step_direction", C.c_int, [_vp, _fp]),
     ("tt_lbfgs_query", C.c_int, [_vp, C.POINTER(C.c_double)]),
     ("tt_lbfgs_run", C.c_int, [_vp, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     ("tt_timing_enable", C.c_int, [_vp, C.c_int]),

@@ -566,7 +566,7 @@ int tt_lbfgs_init(tt_lbfgs *st, float *cin, const float *data, const float *w, d
     return TT_OK;
 }
 
-int tt_lbfgs_step(tt_lbfgs *st)
+static int lbfgs_step_impl(tt_lbfgs *st, const float *user_d)
 {
     if (!st || !st->inited) return fail(TT_EINVAL, "solver not initialised");
     tt_ctx *c = st->ctx;
@@ -581,11 +581,21 @@ int tt_lbfgs_step(tt_lbfgs *st)
     }
     basis[2 * ns] = gold;
     basis[2 * ns + 1] = gnew;
-    {
-        KTimer t(c, TT_K_PLAN);
-        TT_HIP(lbfgs_plan_direction(st->st, st->ist, m, s));
-    }
-    {
+    if (user_d) {
+        // caller's direction: d . b_a for the valid history and the gradient, and d . d
+        {
+            KTimer t(c, TT_K_PLAN);
+            TT_HIP(lbfgs_plan_user_direction(st->st, st->ist, m, s));
+        }
+        KTimer t(c, TT_K_VECTOR);
+        TT_HIP(hipMemcpyAsync(st->d, user_d, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+        TT_HIP(lbfgs_multidot(st->d, basis.data(), 2 * ns + 1, st->ist + kMask, n, st->part, st->st + kDotsD, s));
+        TT_HIP(lbfgs_wnorm2(st->d, nullptr, n, st->part, st->st + kDotsD + kMaxBasis, s));
+    } else {
+        {
+            KTimer t(c, TT_K_PLAN);
+            TT_HIP(lbfgs_plan_direction(st->st, st->ist, m, s));
+        }
         KTimer t(c, TT_K_VECTOR);
         TT_HIP(lbfgs_combine(basis.data(), 2 * ns + 1, st->st + kCoef, st->ist + kMask, n, st->d, st->part,
                              st->st + kDotsD, s));
@@ -624,6 +634,14 @@ int tt_lbfgs_step(tt_lbfgs *st)
     }
     st->gcur = 1 - st->gcur;
     return TT_OK;
+}
+
+int tt_lbfgs_step(tt_lbfgs *st) { return lbfgs_step_impl(st, nullptr); }
+
+int tt_lbfgs_step_direction(tt_lbfgs *st, const float *d_dev)
+{
+    if (!d_dev) return fail(TT_EINVAL, "direction is null");
+    return lbfgs_step_impl(st, d_dev);
 }
 
 int tt_lbfgs_query(tt_lbfgs *st, double *out4)

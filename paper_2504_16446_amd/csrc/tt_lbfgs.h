@@ -39,6 +39,7 @@ constexpr int kStateInts = kMask2 + kMaxBasis + 1;
 struct Dims;
 hipError_t lbfgs_plan_direction(double *st, int *ist, int m, hipStream_t s);
 hipError_t lbfgs_plan_alpha(double *st, int *ist, int m, double mu, hipStream_t s);
+hipError_t lbfgs_plan_user_direction(double *st, int *ist, int m, hipStream_t s);
 hipError_t lbfgs_plan_update(double *st, int *ist, int m, double mu, hipStream_t s);
 hipError_t lbfgs_combine(const float *const *basis, int nb, const double *coef, const int *mask, long long n,
                          float *d, double *partials, double *out, hipStream_t s);

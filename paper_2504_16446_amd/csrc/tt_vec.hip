@@ -290,6 +290,29 @@ __global__ void k_plan_direction(double *st, int *ist, int m)
     ist[kCand] = cand;
 }
 
+// Bookkeeping for a step along a caller-supplied direction: combine mask =
+// the valid history and the gradient, candidate slot = first free slot.
+__global__ void k_plan_user_direction(double *st, int *ist, int m)
+{
+    const int ns = m + 1, nb = 2 * ns + 1;
+    int idx[kMaxBasis];
+    int nidx;
+    valid_list(ist, ns, idx, nidx);
+    for (int a = 0; a < nb; ++a) ist[kMask + a] = 0;
+    for (int q = 0; q < nidx; ++q) ist[kMask + idx[q]] = 1;
+    const int cnt = ist[kCount];
+    int cand = 0;
+    for (int i = 0; i < ns; ++i) {
+        bool used = false;
+        for (int t = 0; t < cnt; ++t) used |= ist[kOrder + t] == i;
+        if (!used) {
+            cand = i;
+            break;
+        }
+    }
+    ist[kCand] = cand;
+}
+
 __global__ void k_plan_alpha(double *st, int *ist, int m, double mu)
 {
     const int ns = m + 1, gi = 2 * ns, nb = 2 * ns + 1;
@@ -375,6 +398,12 @@ __global__ void k_plan_update(double *st, int *ist, int m, double mu)
 hipError_t lbfgs_plan_direction(double *st, int *ist, int m, hipStream_t s)
 {
     hipLaunchKernelGGL(k_plan_direction, dim3(1), dim3(1), 0, s, st, ist, m);
+    return hipGetLastError();
+}
+
+hipError_t lbfgs_plan_user_direction(double *st, int *ist, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plan_user_direction, dim3(1), dim3(1), 0, s, st, ist, m);
     return hipGetLastError();
 }
 

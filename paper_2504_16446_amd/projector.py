@@ -219,6 +219,13 @@ class LBFGS:
         self.projector._bind_stream()
         call("tt_lbfgs_step", self._h)
 
+    def step_direction(self, d: torch.Tensor):
+        """One iteration along d (exact line search along d; the pair enters the history)."""
+        p = self.projector
+        pd = _f32(d, p.vol_shape, "d", p.device)
+        p._bind_stream()
+        call("tt_lbfgs_step_direction", self._h, pd)
+
     def query(self):
         """(loss, ||r||, ||I||, accepted pairs); synchronises."""
         out = (C.c_double * 4)()
