@@ -242,6 +242,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         return fail(TT_EUNSUPPORTED, "more than 16 distinct segments");
     }
     d.Up = d.U <= 4 ? 4 : (d.U <= 8 ? 8 : 16);
+    if (const char *e = std::getenv("TT_ADJOINT_KERNEL")) d.splat = std::strcmp(e, "splat") == 0;
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
