@@ -87,6 +87,7 @@ typedef struct tt_ctx tt_ctx;
  * float64 on the host, uploads device tables and allocates work buffers.
  * Synchronous.  On failure *out is NULL. */
 int tt_create(const tt_geometry *geom, tt_ctx **out);
+/* Waits for the context's stream, then frees its tables and buffers. */
 void tt_destroy(tt_ctx *ctx);
 
 /* Stream for all later device work of this context (a hipStream_t; NULL is
@@ -148,6 +149,7 @@ typedef struct tt_lbfgs tt_lbfgs;
  * vectors and two data vectors).  The data, weight and coefficient buffers
  * passed to tt_lbfgs_init must stay valid while the solver is used. */
 int tt_lbfgs_create(tt_ctx *ctx, int m, tt_lbfgs **out);
+/* Waits for the context's stream, then frees the solver (destroy it before its context). */
 void tt_lbfgs_destroy(tt_lbfgs *st);
 
 /* Start from c_dev (read and updated in place): computes r, L and grad.

@@ -242,7 +242,6 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         return fail(TT_EUNSUPPORTED, "more than 16 distinct segments");
     }
     d.Up = d.U <= 4 ? 4 : (d.U <= 8 ? 8 : 16);
-    if (const char *e = std::getenv("TT_ADJOINT_KERNEL")) d.splat = std::strcmp(e, "splat") == 0;
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -320,6 +319,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
 void tt_destroy(tt_ctx *c)
 {
     if (!c) return;
+    hipStreamSynchronize(c->stream);  // queued kernels may still read these buffers
     tt_timing_enable(c, 0);
     hipFree(c->d_frames);
     hipFree(c->d_Bu);
@@ -483,6 +483,7 @@ int tt_loss_grad(tt_ctx *c, const float *cin, const float *data, const float *w,
 void tt_lbfgs_destroy(tt_lbfgs *st)
 {
     if (!st) return;
+    if (st->ctx) hipStreamSynchronize(st->ctx->stream);
     for (float *p : st->s) hipFree(p);
     for (float *p : st->y) hipFree(p);
     hipFree(st->g[0]);

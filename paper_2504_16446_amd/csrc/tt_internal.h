@@ -48,7 +48,6 @@ struct Dims {
     int S, nj, nk;      // projections and detector
     int nseg, U, Up;    // segments, unique segments, padded unique segments
     float step;
-    int splat = 0;      // adjoint: 1 = ray splat into LDS bricks, 0 = per-voxel gather
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).

@@ -435,101 +435,7 @@ hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *dat
 // backproject: block = brick of 4 (x) x 8 (y) x 8 (z) voxels; wave w owns the
 // x-slice w (64 voxels = 4 column tiles of 16).  Loops over all projections.
 // ---------------------------------------------------------------------------
-// Splat variant of the per-projection segment values Q_s of one brick: every
-// ray that meets the brick's halo box is marched (float64 positions, as in the
-// forward ray march) and each sample adds its trilinear weights times the
-// folded residual into the brick's voxels with LDS atomics.
-template <int UP>
-__device__ __forceinline__ void splat_brick(float (*Qs)[64 * (UP + 1)], const ProjFrame &f, const float *__restrict__ yf,
-                                            int s, int x0, int y0, int z0, int nx, int ny, int nz, int nj, int nk,
-                                            double dstep, int tid)
-{
-    // open box of sample positions (centred coordinates) whose tent support meets the brick
-    const double blo[3] = {x0 - 1 - 0.5 * (nx - 1), y0 - 1 - 0.5 * (ny - 1), z0 - 1 - 0.5 * (nz - 1)};
-    const double bhi[3] = {blo[0] + 5.0, blo[1] + 9.0, blo[2] + 9.0};
-    double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
-#pragma unroll
-    for (int cc = 0; cc < 8; ++cc) {
-        const double px = ((cc & 1) ? bhi[0] : blo[0]) - f.o[0];
-        const double py = ((cc & 2) ? bhi[1] : blo[1]) - f.o[1];
-        const double pz = ((cc & 4) ? bhi[2] : blo[2]) - f.o[2];
-        const double a = px * f.ej[0] + py * f.ej[1] + pz * f.ej[2];
-        const double b = px * f.ek[0] + py * f.ek[1] + pz * f.ek[2];
-        amin = fmin(amin, a);
-        amax = fmax(amax, a);
-        bmin = fmin(bmin, b);
-        bmax = fmax(bmax, b);
-    }
-    const int jlo = max(0, (int)ceil(amin)), jhi = min(nj - 1, (int)floor(amax));
-    const int klo = max(0, (int)ceil(bmin)), khi = min(nk - 1, (int)floor(bmax));
-    const int nJ = jhi - jlo + 1, nK = khi - klo + 1;
-    const int ncand = (nJ > 0 && nK > 0) ? nJ * nK : 0;
-    for (int cnd = tid; cnd < ncand; cnd += 256) {
-        const int j = jlo + cnd / nK, k = klo + cnd % nK;
-        double b0[3], ds[3];
-        double tlo = -1e300, thi = 1e300;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            b0[a] = f.o[a] + j * f.ej[a] + k * f.ek[a];
-            ds[a] = dstep * f.d[a];
-            if (f.inv_d[a] != 0.0) {
-                const double ia = f.inv_d[a] / dstep;
-                const double t1 = (blo[a] - b0[a]) * ia, t2 = (bhi[a] - b0[a]) * ia;
-                tlo = fmax(tlo, fmin(t1, t2));
-                thi = fmin(thi, fmax(t1, t2));
-            } else if (!(b0[a] > blo[a] && b0[a] < bhi[a])) {
-                thi = -1e300;
-            }
-        }
-        if (!(tlo < thi)) continue;
-        const int n0 = (int)ceil(tlo), n1 = (int)floor(thi);
-        if (n0 > n1) continue;
-        float yv[UP];
-        const f4 *yp = reinterpret_cast<const f4 *>(yf + (((long long)s * nj + j) * nk + k) * UP);
-#pragma unroll
-        for (int u4 = 0; u4 < UP; u4 += 4) {
-            const f4 v = yp[u4 / 4];
-            yv[u4] = v.x;
-            yv[u4 + 1] = v.y;
-            yv[u4 + 2] = v.z;
-            yv[u4 + 3] = v.w;
-        }
-        for (int n = n0; n <= n1; ++n) {
-            // local voxel coordinates of the sample: voxel (x0 + l) sits at l
-            const double qx = fma((double)n, ds[0], b0[0]) - blo[0] - 1.0;
-            const double qy = fma((double)n, ds[1], b0[1]) - blo[1] - 1.0;
-            const double qz = fma((double)n, ds[2], b0[2]) - blo[2] - 1.0;
-            const int cx = min(max((int)floor(qx), -1), 3);
-            const int cy = min(max((int)floor(qy), -1), 7);
-            const int cz = min(max((int)floor(qz), -1), 7);
-            const float fx = (float)(qx - cx), fy = (float)(qy - cy), fz = (float)(qz - cz);
-            const float wxs[2] = {1.0f - fx, fx}, wys[2] = {1.0f - fy, fy}, wzs[2] = {1.0f - fz, fz};
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                const int lx = cx + dx;
-                if (lx < 0 || lx > 3) continue;
-#pragma unroll
-                for (int dy = 0; dy < 2; ++dy) {
-                    const int ly = cy + dy;
-                    if (ly < 0 || ly > 7) continue;
-                    const float wxy = wxs[dx] * wys[dy];
-#pragma unroll
-                    for (int dz = 0; dz < 2; ++dz) {
-                        const int lz = cz + dz;
-                        if (lz < 0 || lz > 7) continue;
-                        const float wt = wxy * wzs[dz];
-                        float *qp = &Qs[lx][(ly * 8 + lz) * (UP + 1)];
-#pragma unroll
-                        for (int u = 0; u < UP; ++u)
-                            __hip_atomic_fetch_add(qp + u, wt * yv[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <int UP, int MT, bool BF16, bool SPLAT>
+template <int UP, int MT, bool BF16>
 __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ yf, const ProjFrame *__restrict__ frames,
                                                      const float *__restrict__ Bu, const s4 *__restrict__ BuT16, int S, int nx, int ny, int nz,
                                                      int nj, int nk, int C, int Cp, float step,
@@ -556,13 +462,6 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
     float *Qw = Qs[wave];
     for (int s = 0; s < S; ++s) {
         const ProjFrame &f = frames[s];
-      if constexpr (SPLAT) {
-#pragma unroll
-        for (int u = 0; u < UP; ++u) Qw[lane * (UP + 1) + u] = 0.0f;
-        __syncthreads();
-        splat_brick<UP>(Qs, f, yf, s, bx * 4, by * 8, bz * 8, nx, ny, nz, nj, nk, dstep, tid);
-        __syncthreads();
-      } else {
         float q[UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) q[u] = 0.0f;
@@ -627,7 +526,6 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
 #pragma unroll
         for (int u = 0; u < UP; ++u) Qw[lane * (UP + 1) + u] = q[u];
         __syncthreads();
-      }
         // g tile += B_s^T (coefficients x u) * Q^T (u x voxels)
         if constexpr (BF16) {
             // K = 16 (u padded with zeros): A from BuT16[s][coefficient][u], B = Q rounded to bf16
@@ -703,18 +601,12 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
                        int bf16, float *g, float beta, const float *c, double *partials, hipStream_t st)
 {
     const s4 *bt = reinterpret_cast<const s4 *>(BuT16);
-    const dim3 grid(backproject_blocks(d)), blk(256);
-#define TT_BP_LAUNCH(B, SP)                                                                                      \
-    hipLaunchKernelGGL((k_backproject<UP, MT, B, SP>), grid, blk, 0, st, yf, frames, Bu, bt, d.S, d.nx, d.ny, d.nz, \
-                       d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials)
-    if (d.splat) {
-        if (bf16) TT_BP_LAUNCH(true, true);
-        else TT_BP_LAUNCH(false, true);
-    } else {
-        if (bf16) TT_BP_LAUNCH(true, false);
-        else TT_BP_LAUNCH(false, false);
-    }
-#undef TT_BP_LAUNCH
+    if (bf16)
+        hipLaunchKernelGGL((k_backproject<UP, MT, true>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames, Bu,
+                           bt, d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    else
+        hipLaunchKernelGGL((k_backproject<UP, MT, false>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames,
+                           Bu, bt, d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
     return hipGetLastError();
 }
 

@@ -147,16 +147,3 @@ def test_forward_batches_agree():
     assert P2.batch <= 4 and P1.batch == og.n_proj
     assert torch.equal(P1.forward(_t(c)), P2.forward(_t(c)))
 
-
-@pytest.mark.parametrize("name", ["tiny_offsets_step", "small_l4", "small_l8_seg16", "half_circle_segments", "c1"])
-def test_adjoint_parity_splat_variant(name, monkeypatch):
-    # the alternative adjoint (rays splatted into LDS-resident bricks) is the same operator
-    og = _geom(name)
-    _, y = _inputs(og, 2)
-    ref = oracle.adjoint(og, y)
-    monkeypatch.setenv("TT_ADJOINT_KERNEL", "splat")
-    P = gpu_projector(og)
-    got = _np(P.adjoint(_t(y)))
-    print(name, "splat adjoint rel-L2", rel_l2(got, ref))
-    assert rel_l2(got, ref) <= TOL
-    assert rel_max(got, ref) <= 10 * TOL
