@@ -18,7 +18,7 @@ Pipeline (every numerical step runs in libtt_hip.so):
      ramps; coefficients of order 8 start at 0.
 Training: seeded multi-bundle phantoms at 48^3 / ell_max 6, forward-projected
 on 120 projections, 1% noise, backprojected; MSE against the true
-coefficients; Adam (lr 1e-3 with cosine decay), 20 epochs, batch 8.
+coefficients; Adam (constant lr 1e-3), 20 epochs, batch 8.
 The prediction enters L-BFGS as the first search direction from zero, so the
 exact line search fixes its scale (the geometry normalisation of 48^3
 training volumes and large volumes differs) and adds a curvature pair along it.
@@ -146,17 +146,12 @@ def train(w: synth.Workload, n_phantoms=4096, epochs=20, batch=8, lr=1e-3, devic
     rng = np.random.default_rng(seed + 1)
     nvox = batch * w.n_vox
     history = []
-    steps_per_epoch = n_phantoms // batch
-    total = epochs * steps_per_epoch
-    step = 0
     for ep in range(epochs):
         perm = rng.permutation(n_phantoms)
         tot, nb = 0.0, 0
         for b0 in range(0, n_phantoms - batch + 1, batch):
             idx = torch.from_numpy(perm[b0:b0 + batch]).to(dev)
-            lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / total))  # cosine decay
-            step += 1
-            loss = model.train_step(Xb.index_select(0, idx).contiguous(), Ts.index_select(0, idx).contiguous(), lr_t)
+            loss = model.train_step(Xb.index_select(0, idx).contiguous(), Ts.index_select(0, idx).contiguous(), lr)
             tot += float(loss.item()) if (nb % 64 == 0) else 0.0
             nb += 1
         mse = tot / (len(range(0, nb, 64)) * nvox * NET_CH)
