@@ -238,6 +238,27 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
                   int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Derived per-voxel quantities (the paper's section on deriving standard    */
+/* quantities from the output: mean intensity, second-moment tensor and its  */
+/* eigendecomposition, fractional anisotropy; plus the spherical variance    */
+/* and relative anisotropy that the basis-set properties list).              */
+/* ------------------------------------------------------------------------ */
+#define TT_PROP_FIELDS 22
+/* c: device float [n_vox][C], C = tt_num_coeffs-style count for ell_max
+ * (even, 0..16).  out: device float [n_vox][TT_PROP_FIELDS], per voxel:
+ *   0 mean <f>, 1 variance <(f - <f>)^2>, 2 relative anisotropy sqrt(var)/mean,
+ *   3..8 second-moment tensor M_ab = <q_a q_b f> as xx, yy, zz, xy, xz, yz,
+ *   9..11 eigenvalues of M in descending order,
+ *   12..20 the matching unit eigenvectors (x, y, z each), each with its
+ *          largest-magnitude component positive,
+ *   21 fractional anisotropy of the eigenvalues,
+ * where f(q) = sum_i c_i Y_i(q) and <g> is the average over the unit sphere.
+ * Sums and the eigensolver run in float64.  c and out must be 16-byte
+ * aligned (TT_EINVAL otherwise); with n_vox = 0 nothing is accessed.
+ * Asynchronous on `stream`. */
+int tt_tensor_properties(const float *c, int64_t n_vox, int ell_max, float *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Optional kernel timing: when enabled, every kernel launch of the context  */
 /* is bracketed by HIP events on the context's stream, per kernel class.     */
 /* ------------------------------------------------------------------------ */

@@ -80,6 +80,7 @@ _SIGS = [
                                  C.c_int, _vp, C.c_int, C.c_int, _fp, _fp, C.c_int, C.c_int, _vp, _vp]),
     ("tt_tile_blend", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp,
                                 C.c_int, C.c_int, C.c_int, C.c_int, _fp, _vp]),
+    ("tt_tensor_properties", C.c_int, [_fp, C.c_int64, C.c_int, _fp, _vp]),
     ("tt_last_error", C.c_char_p, []),
     ("tt_error_string", C.c_char_p, [C.c_int]),
 ]

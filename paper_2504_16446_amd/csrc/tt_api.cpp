@@ -242,6 +242,8 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         return fail(TT_EUNSUPPORTED, "more than 16 distinct segments");
     }
     d.Up = d.U <= 4 ? 4 : (d.U <= 8 ? 8 : 16);
+    // staged march: at most 48 KiB of LDS per 256-ray tile (three tiles per CU)
+    d.march_lds = plan_slabs(c->frames, d.Up, 48 * 1024);
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -784,6 +786,20 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
         nty < 1 || ntz < 1)
         return fail(TT_ESHAPE, "bad sizes");
     TT_HIP(net_tile_blend(y, cy, creal, X, Y, Z, ox, ntx, oy, nty, oz, ntz, T, ramp, cout, out, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_tensor_properties(const float *c, int64_t n_vox, int ell_max, float *out, void *stream)
+{
+    if (ell_max < 0 || ell_max % 2) return fail(TT_EINVAL, "ell_max must be even and >= 0");
+    if (ell_max > 16) return fail(TT_EUNSUPPORTED, "ell_max above 16");
+    if (n_vox < 0) return fail(TT_ESHAPE, "n_vox must be >= 0");
+    if (n_vox == 0) return TT_OK;  // nothing to read or write: any pointers accepted
+    if (!c || !out) return fail(TT_EINVAL, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(out)) % 16)
+        return fail(TT_EINVAL, "c and out must be 16-byte aligned");
+    static_assert(TT_PROP_FIELDS == kPropFields, "field count");
+    TT_HIP(launch_tensor_props(c, n_vox, num_coeffs(ell_max), out, (hipStream_t)stream));
     return TT_OK;
 }
 

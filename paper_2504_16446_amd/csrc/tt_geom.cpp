@@ -194,4 +194,45 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
     }
 }
 
+// Slab plan of the staged march.  For a tile of T x T parallel rays and a
+// slab of W planes of axis A, the samples of the slab lie in the parallelepiped
+// spanned by the tile's corner rays between the planes; its extent along the
+// other two axes does not depend on where the tile sits, so one (eb, ez) per
+// projection bounds every tile's staged box (+2 for the corner cells and
+// rounding, +2 for the one-voxel margin on each side).
+int plan_slabs(std::vector<ProjFrame> &frames, int up, int lds_budget)
+{
+    constexpr int kMaxSlab = 8;
+    const double T = kMarchTile - 1;
+    int most = 0;
+    for (ProjFrame &f : frames) {
+        const int A = std::fabs(f.d[0]) >= std::fabs(f.d[1]) ? 0 : 1, B = 1 - A;
+        f.slab_a = A;
+        f.slab_w = f.slab_eb = f.slab_ez = 0;
+        if (std::fabs(f.d[A]) < 0.25) continue;  // steep rays: many samples per plane
+        for (int W = kMaxSlab; W >= 1; --W) {
+            double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+            for (int v = 0; v < 8; ++v) {
+                const double J = (v & 1) ? T : 0.0, K = (v & 2) ? T : 0.0, P = (v & 4) ? W : 0.0;
+                const double t = (P - J * f.ej[A] - K * f.ek[A]) / f.d[A];
+                const double q[2] = {J * f.ej[B] + K * f.ek[B] + t * f.d[B], J * f.ej[2] + K * f.ek[2] + t * f.d[2]};
+                for (int a = 0; a < 2; ++a) {
+                    lo[a] = std::min(lo[a], q[a]);
+                    hi[a] = std::max(hi[a], q[a]);
+                }
+            }
+            const int eb = (int)std::floor(hi[0] - lo[0]) + 5, ez = (int)std::floor(hi[1] - lo[1]) + 5;
+            const long long bytes = (long long)(W + 1) * eb * ez * up * (long long)sizeof(float);
+            if (bytes <= lds_budget) {
+                f.slab_w = W;
+                f.slab_eb = eb;
+                f.slab_ez = ez;
+                most = std::max(most, (int)bytes);
+                break;
+            }
+        }
+    }
+    return most;
+}
+
 }  // namespace tt

@@ -33,11 +33,23 @@ struct ProjFrame {
     float hull[12];
     float ejf[3], ekf[3], df[3];  // float copies for the small offsets inside the cube
     float inv_df[3];              // 1 / d_a or 0
+    // Slab plan of the LDS-staged march (tiles of kMarchTile x kMarchTile
+    // rays): slabs are planes of axis slab_a (0 = x, 1 = y); each slab holds
+    // the samples whose cell lies in slab_w consecutive planes, and stages a
+    // box of (slab_w + 1) x slab_eb (the other horizontal axis) x slab_ez (z)
+    // voxels that contains every corner those samples touch.  slab_w = 0:
+    // the projection's rays gather from global memory instead.
+    int slab_a, slab_w, slab_eb, slab_ez;
 };
+
+constexpr int kMarchTile = 16;  // rays per tile edge in the forward march
 
 int num_coeffs(int ell_max);
 void sh_eval_one(int ell_max, const double *dir, double *out);
 void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector<double> &B);
+// Fills the slab plan of every frame for staged voxels of `up` floats within
+// `lds_budget` bytes; returns the largest staging size in bytes (0 if none).
+int plan_slabs(std::vector<ProjFrame> &frames, int up, int lds_budget);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (tt_proj.hip, tt_vec.hip).  All asynchronous on `st`.
@@ -48,6 +60,7 @@ struct Dims {
     int S, nj, nk;      // projections and detector
     int nseg, U, Up;    // segments, unique segments, padded unique segments
     float step;
+    int march_lds;      // dynamic LDS bytes of the staged march (0: no projection staged)
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
@@ -72,6 +85,10 @@ hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const floa
                               const float *Bu, const uint16_t *BuT16, int bf16, float *g, float beta,
                               const float *c, double *partials, hipStream_t st);
 int backproject_blocks(const Dims &d);
+
+// Derived per-voxel quantities: out[v][kPropFields] from c[v][C] (tt_props.hip).
+constexpr int kPropFields = 22;
+hipError_t launch_tensor_props(const float *c, long long nvox, int C, float *out, hipStream_t st);
 
 // Reductions: out[slot] = scale * sum of partials[0..n).
 hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,

@@ -239,24 +239,22 @@ hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bsw16,
 // march: one thread per ray; block = 16 (j) x 16 (k) rays of one projection.
 // Positions are float64 in padded index coordinates (voxel ix sits at ix + 1,
 // borders of M are zero), so no bounds test is needed inside the loop.
+//
+// The tile's rays are marched slab by slab: a slab is W planes of the
+// horizontal axis A most aligned with the rays.  Before each slab the block
+// stages the box of M that holds every corner its samples touch into LDS
+// (rows along z, coalesced), then each thread walks its own samples in that
+// slab and gathers the 8 corners from LDS.  The box size comes from the
+// per-projection slab plan; projections without a plan (steep rays) gather
+// straight from global memory.
 // ---------------------------------------------------------------------------
-template <int UP>
-__global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
-                                               int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
-                                               float step, long long vol_pad, float *__restrict__ I)
+
+// Ray setup shared by both paths: index-space base point b and step ds of the
+// ray through pixel (j, k), and its sample range [n0, n1] (empty if n0 > n1).
+__device__ __forceinline__ void ray_setup(const ProjFrame &f, int j, int k, int nx, int ny, int nz, float step,
+                                          double b[3], double ds[3], int &n0, int &n1)
 {
-    // tile: projection-major, then 16x16 ray tiles (dispatch order; an
-    // XCD-contiguous remap measured slower here)
-    const int ntj = (nj + 15) / 16, ntk = (nk + 15) / 16;
-    const int lb = blockIdx.x;
-    const int p = lb / (ntj * ntk), s = s0 + p;
-    const int tj = (lb / ntk) % ntj, tk = lb % ntk;
-    const int j = tj * 16 + (threadIdx.x & 15);
-    const int k = tk * 16 + (threadIdx.x >> 4);
-    if (j >= nj || k >= nk) return;
-    const ProjFrame &f = frames[s];
     const double n3[3] = {(double)nx, (double)ny, (double)nz};
-    double b[3], ds[3];
     double tlo = -1e300, thi = 1e300;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -272,39 +270,164 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
             thi = -1e300;
         }
     }
+    n0 = 0;
+    n1 = -1;
+    if (tlo < thi) {
+        n0 = (int)ceil(tlo);
+        n1 = (int)floor(thi);
+    }
+}
+
+template <int UP>
+__device__ __forceinline__ void march_global(const float *__restrict__ Mp, const double b[3], const double ds[3], int n0,
+                                             int n1, int nx, int ny, int nz, float acc[UP])
+{
+    const long long sz = UP, sy = (long long)(nz + 2) * UP, sx = (long long)(ny + 2) * sy;
+    for (int n = n0; n <= n1; ++n) {
+        double px = fma((double)n, ds[0], b[0]);
+        double py = fma((double)n, ds[1], b[1]);
+        double pz = fma((double)n, ds[2], b[2]);
+        int ix = min(max((int)floor(px), 0), nx);
+        int iy = min(max((int)floor(py), 0), ny);
+        int iz = min(max((int)floor(pz), 0), nz);
+        float fx = (float)(px - ix), fy = (float)(py - iy), fz = (float)(pz - iz);
+        float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+        float w00 = gx * gy, w01 = gx * fy, w10 = fx * gy, w11 = fx * fy;
+        const float *q = Mp + ix * sx + iy * sy + iz * sz;
+        float w[8] = {w00 * gz, w00 * fz, w01 * gz, w01 * fz, w10 * gz, w10 * fz, w11 * gz, w11 * fz};
+        const long long off[8] = {0, sz, sy, sy + sz, sx, sx + sz, sx + sy, sx + sy + sz};
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+#pragma unroll
+            for (int u4 = 0; u4 < UP; u4 += 4) {
+                f4 m = *reinterpret_cast<const f4 *>(q + off[cc] + u4);
+                acc[u4 + 0] = fmaf(w[cc], m.x, acc[u4 + 0]);
+                acc[u4 + 1] = fmaf(w[cc], m.y, acc[u4 + 1]);
+                acc[u4 + 2] = fmaf(w[cc], m.z, acc[u4 + 2]);
+                acc[u4 + 3] = fmaf(w[cc], m.w, acc[u4 + 3]);
+            }
+        }
+    }
+}
+
+template <int UP>
+__global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
+                                               int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
+                                               float step, long long vol_pad, float *__restrict__ I)
+{
+    constexpr int Q = UP / 4;      // float4 per staged voxel
+    extern __shared__ f4 box[];    // [W + 1][eb][ez][Q]
+    __shared__ int arange[2];
+    const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
+    const int lb = blockIdx.x;
+    const int p = lb / (ntj * ntk), s = s0 + p;
+    const int tj = (lb / ntk) % ntj, tk = lb % ntk;
+    const int j = tj * kMarchTile + (threadIdx.x % kMarchTile);
+    const int k = tk * kMarchTile + (threadIdx.x / kMarchTile);
+    const bool live = j < nj && k < nk;
+    const ProjFrame &f = frames[s];
+    const float *Mp = M + (long long)p * vol_pad * UP;
+    double b[3], ds[3];
+    int n0 = 0, n1 = -1;
+    if (live) ray_setup(f, j, k, nx, ny, nz, step, b, ds, n0, n1);
     float acc[UP];
 #pragma unroll
     for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
-    if (tlo < thi) {
-        const int n0 = (int)ceil(tlo), n1 = (int)floor(thi);
-        const long long sz = UP, sy = (long long)(nz + 2) * UP, sx = (long long)(ny + 2) * sy;
-        const float *Mp = M + (long long)p * vol_pad * UP;
-        for (int n = n0; n <= n1; ++n) {
-            double px = fma((double)n, ds[0], b[0]);
-            double py = fma((double)n, ds[1], b[1]);
-            double pz = fma((double)n, ds[2], b[2]);
-            int ix = min(max((int)floor(px), 0), nx);
-            int iy = min(max((int)floor(py), 0), ny);
-            int iz = min(max((int)floor(pz), 0), nz);
-            float fx = (float)(px - ix), fy = (float)(py - iy), fz = (float)(pz - iz);
-            float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
-            float w00 = gx * gy, w01 = gx * fy, w10 = fx * gy, w11 = fx * fy;
-            const float *q = Mp + ix * sx + iy * sy + iz * sz;
-            float w[8] = {w00 * gz, w00 * fz, w01 * gz, w01 * fz, w10 * gz, w10 * fz, w11 * gz, w11 * fz};
-            const long long off[8] = {0, sz, sy, sy + sz, sx, sx + sz, sx + sy, sx + sy + sz};
+
+    const int W = f.slab_w;
+    if (W == 0) {
+        if (n0 <= n1) march_global<UP>(Mp, b, ds, n0, n1, nx, ny, nz, acc);
+    } else {
+        const int A = f.slab_a, B = 1 - A, EB = f.slab_eb, EZ = f.slab_ez;
+        // samples are visited in increasing index coordinate along A
+        const bool fwd = f.d[A] > 0.0;
+        const int count = n1 - n0 + 1;
+        if (threadIdx.x == 0) {
+            arange[0] = INT_MAX;
+            arange[1] = INT_MIN;
+        }
+        __syncthreads();
+        if (count > 0) {
+            const int nf = fwd ? n0 : n1, nl = fwd ? n1 : n0;
+            atomicMin(&arange[0], (int)floor(fma((double)nf, ds[A], b[A])));
+            atomicMax(&arange[1], (int)floor(fma((double)nl, ds[A], b[A])));
+        }
+        __syncthreads();
+        const int amin = arange[0], amax = arange[1];
+        // tile origin ray (possibly outside the detector: only its geometry is used)
+        const double n3[3] = {(double)nx, (double)ny, (double)nz};
+        double b00[3];
 #pragma unroll
-            for (int cc = 0; cc < 8; ++cc) {
+        for (int a = 0; a < 3; ++a)
+            b00[a] = f.o[a] + (tj * kMarchTile) * f.ej[a] + (tk * kMarchTile) * f.ek[a] + 0.5 * (n3[a] + 1.0);
+        const double dA = (double)step * f.d[A], dB = (double)step * f.d[B], dZ = (double)step * f.d[2];
+        const double T = kMarchTile - 1;
+        const int plane = EB * EZ, nbox = (W + 1) * plane;
+        const float inv_plane = 1.0f / (float)plane, inv_ez = 1.0f / (float)EZ;
+        const int da = plane * Q, db = EZ * Q, dz = Q;
+        int m = 0;
+        for (int A0 = amin; A0 <= amax; A0 += W) {
+            // staged box origin: the lowest corner of the tile's rays between planes A0 and A0 + W
+            double mb = 1e300, mz = 1e300;
 #pragma unroll
-                for (int u4 = 0; u4 < UP; u4 += 4) {
-                    f4 m = *reinterpret_cast<const f4 *>(q + off[cc] + u4);
-                    acc[u4 + 0] = fmaf(w[cc], m.x, acc[u4 + 0]);
-                    acc[u4 + 1] = fmaf(w[cc], m.y, acc[u4 + 1]);
-                    acc[u4 + 2] = fmaf(w[cc], m.z, acc[u4 + 2]);
-                    acc[u4 + 3] = fmaf(w[cc], m.w, acc[u4 + 3]);
+            for (int v = 0; v < 8; ++v) {
+                const double J = (v & 1) ? T : 0.0, K = (v & 2) ? T : 0.0, P = (v & 4) ? (double)(A0 + W) : (double)A0;
+                const double t = (P - (b00[A] + J * f.ej[A] + K * f.ek[A])) / dA;
+                mb = fmin(mb, b00[B] + J * f.ej[B] + K * f.ek[B] + t * dB);
+                mz = fmin(mz, b00[2] + J * f.ej[2] + K * f.ek[2] + t * dZ);
+            }
+            const int B0 = (int)floor(mb) - 1, Z0 = (int)floor(mz) - 1;
+            __syncthreads();  // the previous slab's gathers are done
+            for (int e = threadIdx.x; e < nbox; e += 256) {
+                const int pl = (int)(((float)e + 0.5f) * inv_plane);
+                const int r = e - pl * plane;
+                const int ib = (int)(((float)r + 0.5f) * inv_ez);
+                const int gz = Z0 + (r - ib * EZ), ga = A0 + pl, gb = B0 + ib;
+                const int gx = A == 0 ? ga : gb, gy = A == 0 ? gb : ga;
+                f4 v[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) v[q] = f4{0.f, 0.f, 0.f, 0.f};
+                if (gx >= 0 && gx <= nx + 1 && gy >= 0 && gy <= ny + 1 && gz >= 0 && gz <= nz + 1) {
+                    const f4 *src = reinterpret_cast<const f4 *>(Mp + (((long long)gx * (ny + 2) + gy) * (nz + 2) + gz) * UP);
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) v[q] = src[q];
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) box[e * Q + q] = v[q];
+            }
+            __syncthreads();
+            for (; m < count; ++m) {
+                const int n = fwd ? n0 + m : n1 - m;
+                const double pa = fma((double)n, ds[A], b[A]);
+                const int ia = (int)floor(pa);
+                if (ia >= A0 + W) break;  // belongs to a later slab
+                const double pb = fma((double)n, ds[B], b[B]);
+                const double pz = fma((double)n, ds[2], b[2]);
+                const int ibb = (int)floor(pb), izz = (int)floor(pz);
+                const float fa = (float)(pa - ia), fb = (float)(pb - ibb), fz = (float)(pz - izz);
+                const int la = min(max(ia - A0, 0), W - 1);
+                const int lbb = min(max(ibb - B0, 0), EB - 2);
+                const int lz = min(max(izz - Z0, 0), EZ - 2);
+                const float ga_ = 1.0f - fa, gb_ = 1.0f - fb, gz_ = 1.0f - fz;
+                const float w00 = ga_ * gb_, w01 = ga_ * fb, w10 = fa * gb_, w11 = fa * fb;
+                const float w[8] = {w00 * gz_, w00 * fz, w01 * gz_, w01 * fz, w10 * gz_, w10 * fz, w11 * gz_, w11 * fz};
+                const int off[8] = {0, dz, db, db + dz, da, da + dz, da + db, da + db + dz};
+                const int base = ((la * EB + lbb) * EZ + lz) * Q;
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc) {
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const f4 mv = box[base + off[cc] + q];
+                        acc[4 * q + 0] = fmaf(w[cc], mv.x, acc[4 * q + 0]);
+                        acc[4 * q + 1] = fmaf(w[cc], mv.y, acc[4 * q + 1]);
+                        acc[4 * q + 2] = fmaf(w[cc], mv.z, acc[4 * q + 2]);
+                        acc[4 * q + 3] = fmaf(w[cc], mv.w, acc[4 * q + 3]);
+                    }
                 }
             }
         }
     }
+    if (!live) return;
     float *out = I + (((long long)s * nj + j) * nk + k) * nseg;
 #pragma unroll
     for (int u = 0; u < UP; ++u) {
@@ -319,9 +442,9 @@ static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M
                           hipStream_t st)
 {
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
-    dim3 grid(((d.nk + 15) / 16) * ((d.nj + 15) / 16) * np);
-    hipLaunchKernelGGL(k_march<UP>, grid, dim3(256), 0, st, M, frames, s0, d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg,
-                       d.U, d.step, vol_pad, I);
+    dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * np);
+    hipLaunchKernelGGL(k_march<UP>, grid, dim3(kMarchTile * kMarchTile), d.march_lds, st, M, frames, s0, d.nx, d.ny,
+                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I);
     return hipGetLastError();
 }
 

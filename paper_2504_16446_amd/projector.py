@@ -14,7 +14,8 @@ import torch
 from . import _lib, synth
 from ._lib import Geometry, call, lib
 
-__all__ = ["Projector", "ProjectFn", "project", "LBFGS", "sh_eval", "num_coeffs"]
+__all__ = ["Projector", "ProjectFn", "project", "LBFGS", "sh_eval", "num_coeffs", "tensor_properties",
+           "PROPERTY_FIELDS"]
 
 
 def num_coeffs(ell_max: int) -> int:
@@ -241,3 +242,35 @@ class LBFGS:
         call("tt_lbfgs_run", self._h, int(max_iter), float(rel_tol),
              hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(it))
         return it.value, hist[: it.value]
+
+
+# Column order of tensor_properties (matches TT_PROP_FIELDS in tt.h).
+PROPERTY_FIELDS = ("mean", "variance", "rel_anisotropy",
+                   "m_xx", "m_yy", "m_zz", "m_xy", "m_xz", "m_yz",
+                   "lambda1", "lambda2", "lambda3",
+                   "v1_x", "v1_y", "v1_z", "v2_x", "v2_y", "v2_z", "v3_x", "v3_y", "v3_z",
+                   "fa")
+
+
+def tensor_properties(c: torch.Tensor, ell_max: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Derived per-voxel quantities of coefficients c[..., C]: tensor [..., 22].
+
+    Mean, variance, relative anisotropy, second-moment tensor, its eigenvalues
+    (descending) and eigenvectors, and the fractional anisotropy, in the order
+    of PROPERTY_FIELDS.  Runs on the current HIP stream.
+    """
+    C_ = num_coeffs(ell_max)
+    if not isinstance(c, torch.Tensor) or c.dtype != torch.float32 or not c.is_cuda or not c.is_contiguous():
+        raise ValueError("c must be a contiguous float32 device tensor")
+    if c.shape[-1] != C_:
+        raise ValueError(f"c has {c.shape[-1]} coefficients, expected {C_} for ell_max {ell_max}")
+    n_vox = c.numel() // C_
+    shape = tuple(c.shape[:-1]) + (len(PROPERTY_FIELDS),)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=c.device)
+    _f32(out, shape, "out", c.device)
+    stream = torch.cuda.current_stream(c.device).cuda_stream
+    call("tt_tensor_properties", C.c_void_p(c.data_ptr()), n_vox, int(ell_max), C.c_void_p(out.data_ptr()),
+         C.c_void_p(stream))
+    return out
+

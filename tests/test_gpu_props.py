@@ -1,0 +1,91 @@
+"""GPU parity of the derived per-voxel quantities against the FP64 oracle.
+
+The kernel reads float32 coefficients and evaluates in float64; the oracle
+gets the same float32 values.  Scalars (mean, variance, tensor, eigenvalues,
+anisotropies) must agree to 1e-6 relative (rel-L2 per field over the voxels;
+fields that vanish are measured against their natural scale: the mean for the
+tensor and eigenvalues, its square for the variance, 1 for the ratios), and
+every element to 1e-5 of max(|value|, scale).  Eigenvectors are unique
+only up to sign and only where the eigenvalue is separated from the others:
+they are compared where the relative gap exceeds 1e-3, as |v . v_ref| >= 1 -
+1e-5, and component-wise (sign convention included) where the largest
+component leads the second largest by 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.derived import FIELDS, tensor_properties as oracle_props
+from paper_2504_16446_amd import synth
+from paper_2504_16446_amd.projector import PROPERTY_FIELDS, tensor_properties
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+F = {n: i for i, n in enumerate(FIELDS)}
+
+
+def _coeffs(n_vox, ell_max, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal((n_vox, oracle.num_coeffs(ell_max))).astype(np.float32)
+    c[:, 0] += 4.0  # positive means
+    return c
+
+
+def _check(got, ref):
+    assert got.shape == ref.shape
+    mean = np.abs(ref[:, F["mean"]])
+    scales = {"mean": mean, "variance": mean ** 2, "rel_anisotropy": np.ones_like(mean), "fa": np.ones_like(mean)}
+    for name in ("mean", "variance", "rel_anisotropy", "m_xx", "m_yy", "m_zz", "m_xy", "m_xz", "m_yz",
+                 "lambda1", "lambda2", "lambda3", "fa"):
+        g, r = got[:, F[name]], ref[:, F[name]]
+        sc = scales.get(name, mean)
+        err = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-6 * np.linalg.norm(sc))
+        assert err <= 1e-6, (name, err)
+        assert np.all(np.abs(g - r) <= 1e-5 * np.maximum(np.abs(r), sc)), name
+    lam = ref[:, [F["lambda1"], F["lambda2"], F["lambda3"]]]
+    lmax = np.abs(lam).max(1) + 1e-30
+    for i in range(3):
+        others = [o for o in range(3) if o != i]
+        gap = np.min(np.abs(lam[:, [i]] - lam[:, others]), axis=1) / lmax
+        sel = gap > 1e-3
+        cols = [F[f"v{i + 1}_{a}"] for a in "xyz"]
+        vg, vr = got[sel][:, cols], ref[sel][:, cols]
+        assert np.all(np.abs((vg * vr).sum(1)) >= 1 - 1e-5), i
+        s = np.sort(np.abs(vr), axis=1)
+        lead = (s[:, 2] - s[:, 1]) > 1e-3
+        assert np.all(np.abs(vg[lead] - vr[lead]) <= 1e-5), i
+
+
+@pytest.mark.parametrize("ell_max,n_vox", [(0, 77), (2, 200), (4, 1), (6, 1037), (8, 4160 + 23), (16, 130)])
+def test_properties_parity(ell_max, n_vox):
+    assert tuple(PROPERTY_FIELDS) == tuple(FIELDS)
+    c = _coeffs(n_vox, ell_max, 31 + ell_max)
+    got = tensor_properties(torch.from_numpy(c).to(DEV), ell_max).cpu().numpy().astype(np.float64)
+    ref = oracle_props(c.astype(np.float64), ell_max)
+    _check(got, ref)
+
+
+def test_properties_empty_and_shape():
+    c = torch.zeros((0, 45), device=DEV)
+    out = tensor_properties(c, 8)
+    assert tuple(out.shape) == (0, 22)
+    c = torch.from_numpy(_coeffs(6 * 5 * 4, 4, 3).reshape(6, 5, 4, 15)).to(DEV)
+    assert tuple(tensor_properties(c, 4).shape) == (6, 5, 4, 22)
+
+
+def test_properties_full_size_sampled():
+    """256^3 voxels at ell_max 8 (the largest reconstruction workload) in one launch; sampled voxels checked."""
+    w = synth.WORKLOADS["c5"]
+    g = torch.Generator(device=DEV)
+    g.manual_seed(1234)
+    c = torch.randn((w.n_vox, w.n_coeff), device=DEV, generator=g)
+    c[:, 0] += 4.0
+    got = tensor_properties(c, w.ell_max)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = np.concatenate([rng.integers(0, w.n_vox, 4000), [0, w.n_vox - 1]])
+    it = torch.from_numpy(idx).to(DEV)
+    sub = got[it].cpu().numpy().astype(np.float64)
+    ref = oracle_props(c[it].cpu().numpy().astype(np.float64), w.ell_max)
+    _check(sub, ref)

@@ -93,3 +93,17 @@ def test_product_never_imports_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "tt_oracle" not in text, f
+
+
+def test_tensor_properties_argument_errors_without_device():
+    lib = _lib().lib()
+    buf = (C.c_float * 64)()
+    p = C.cast(buf, C.c_void_p)
+    assert lib.tt_tensor_properties(None, 1, 2, p, None) == -1
+    assert lib.tt_tensor_properties(None, 0, 2, None, None) == 0
+    assert lib.tt_tensor_properties(p, 1, 3, p, None) == -1
+    assert lib.tt_tensor_properties(p, 1, 18, p, None) == -6
+    assert lib.tt_tensor_properties(p, -1, 2, p, None) == -2
+    assert lib.tt_tensor_properties(p, 0, 2, p, None) == 0
+    odd = C.c_void_p(C.addressof(buf) + 4)
+    assert lib.tt_tensor_properties(odd, 1, 2, p, None) == -1
