@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
                                                float step, long long vol_pad, float *__restrict__ I)
 {
     constexpr int Q = UP / 4;      // float4 per staged voxel
-    extern __shared__ f4 box[];    // [W + 1][eb][ez][Q]
+    extern __shared__ f4 box[];    // [Q][W + 1][eb][ez]
     __shared__ int arange[2];
     const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
     const int lb = blockIdx.x;
@@ -354,46 +354,65 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
         }
         __syncthreads();
         const int amin = arange[0], amax = arange[1];
-        // tile origin ray (possibly outside the detector: only its geometry is used)
+        // Staged box origin of slab A0: the lowest corner, along B and z, of the
+        // tile's rays between planes A0 and A0 + W.  Each vertex coordinate is
+        // affine in A0 with the common slope d_B / d_A (resp. d_z / d_A), so the
+        // minimum over the 8 vertices is kb + A0 rB (resp. kz + A0 rZ).
         const double n3[3] = {(double)nx, (double)ny, (double)nz};
         double b00[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             b00[a] = f.o[a] + (tj * kMarchTile) * f.ej[a] + (tk * kMarchTile) * f.ek[a] + 0.5 * (n3[a] + 1.0);
-        const double dA = (double)step * f.d[A], dB = (double)step * f.d[B], dZ = (double)step * f.d[2];
+        const double rB = f.d[B] * f.inv_d[A], rZ = f.d[2] * f.inv_d[A];
         const double T = kMarchTile - 1;
+        double kb = 1e300, kz = 1e300;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const double J = (v & 1) ? T : 0.0, K = (v & 2) ? T : 0.0, P = (v & 4) ? (double)W : 0.0;
+            const double t = P - (b00[A] + J * f.ej[A] + K * f.ek[A]);
+            kb = fmin(kb, b00[B] + J * f.ej[B] + K * f.ek[B] + t * rB);
+            kz = fmin(kz, b00[2] + J * f.ej[2] + K * f.ek[2] + t * rZ);
+        }
         const int plane = EB * EZ, nbox = (W + 1) * plane;
         const float inv_plane = 1.0f / (float)plane, inv_ez = 1.0f / (float)EZ;
-        const int da = plane * Q, db = EZ * Q, dz = Q;
+        // M strides (in voxels) of the box axes A and B; z is contiguous
+        const int sy = nz + 2, sx = (ny + 2) * sy;
+        const int sA = A == 0 ? sx : sy, sB = A == 0 ? sy : sx;
+        const unsigned nAp = (A == 0 ? nx : ny) + 1, nBp = (A == 0 ? ny : nx) + 1, nZp = nz + 1;
+        // LDS layout box[q][e]: the q-th float4 of all staged voxels, then the next
+        const int da = plane, db = EZ, dz = 1;
         int m = 0;
         for (int A0 = amin; A0 <= amax; A0 += W) {
-            // staged box origin: the lowest corner of the tile's rays between planes A0 and A0 + W
-            double mb = 1e300, mz = 1e300;
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const double J = (v & 1) ? T : 0.0, K = (v & 2) ? T : 0.0, P = (v & 4) ? (double)(A0 + W) : (double)A0;
-                const double t = (P - (b00[A] + J * f.ej[A] + K * f.ek[A])) / dA;
-                mb = fmin(mb, b00[B] + J * f.ej[B] + K * f.ek[B] + t * dB);
-                mz = fmin(mz, b00[2] + J * f.ej[2] + K * f.ek[2] + t * dZ);
-            }
-            const int B0 = (int)floor(mb) - 1, Z0 = (int)floor(mz) - 1;
+            const int B0 = (int)floor(fma((double)A0, rB, kb)) - 1, Z0 = (int)floor(fma((double)A0, rZ, kz)) - 1;
+            const long long org = (long long)A0 * sA + (long long)B0 * sB + Z0;  // may lie outside M
             __syncthreads();  // the previous slab's gathers are done
-            for (int e = threadIdx.x; e < nbox; e += 256) {
-                const int pl = (int)(((float)e + 0.5f) * inv_plane);
-                const int r = e - pl * plane;
-                const int ib = (int)(((float)r + 0.5f) * inv_ez);
-                const int gz = Z0 + (r - ib * EZ), ga = A0 + pl, gb = B0 + ib;
-                const int gx = A == 0 ? ga : gb, gy = A == 0 ? gb : ga;
-                f4 v[Q];
+            constexpr int KB = 4;  // staged voxels per thread in flight
+            for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * KB) {
+                f4 v[KB][Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) v[q] = f4{0.f, 0.f, 0.f, 0.f};
-                if (gx >= 0 && gx <= nx + 1 && gy >= 0 && gy <= ny + 1 && gz >= 0 && gz <= nz + 1) {
-                    const f4 *src = reinterpret_cast<const f4 *>(Mp + (((long long)gx * (ny + 2) + gy) * (nz + 2) + gz) * UP);
+                for (int kk = 0; kk < KB; ++kk) {
+                    const int e = e0 + 256 * kk;
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) v[q] = src[q];
+                    for (int q = 0; q < Q; ++q) v[kk][q] = f4{0.f, 0.f, 0.f, 0.f};
+                    const int pl = (int)(((float)e + 0.5f) * inv_plane);
+                    const int r = e - pl * plane;
+                    const int ib = (int)(((float)r + 0.5f) * inv_ez);
+                    const int iz = r - ib * EZ;
+                    if (e < nbox && (unsigned)(A0 + pl) <= nAp && (unsigned)(B0 + ib) <= nBp &&
+                        (unsigned)(Z0 + iz) <= nZp) {
+                        const f4 *src = reinterpret_cast<const f4 *>(Mp + (org + pl * sA + ib * sB + iz) * UP);
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) v[kk][q] = src[q];
+                    }
                 }
 #pragma unroll
-                for (int q = 0; q < Q; ++q) box[e * Q + q] = v[q];
+                for (int kk = 0; kk < KB; ++kk) {
+                    const int e = e0 + 256 * kk;
+                    if (e < nbox) {
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) box[q * nbox + e] = v[kk][q];
+                    }
+                }
             }
             __syncthreads();
             for (; m < count; ++m) {
@@ -412,12 +431,12 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
                 const float w00 = ga_ * gb_, w01 = ga_ * fb, w10 = fa * gb_, w11 = fa * fb;
                 const float w[8] = {w00 * gz_, w00 * fz, w01 * gz_, w01 * fz, w10 * gz_, w10 * fz, w11 * gz_, w11 * fz};
                 const int off[8] = {0, dz, db, db + dz, da, da + dz, da + db, da + db + dz};
-                const int base = ((la * EB + lbb) * EZ + lz) * Q;
+                const int base = (la * EB + lbb) * EZ + lz;
 #pragma unroll
                 for (int cc = 0; cc < 8; ++cc) {
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const f4 mv = box[base + off[cc] + q];
+                        const f4 mv = box[q * nbox + base + off[cc]];
                         acc[4 * q + 0] = fmaf(w[cc], mv.x, acc[4 * q + 0]);
                         acc[4 * q + 1] = fmaf(w[cc], mv.y, acc[4 * q + 1]);
                         acc[4 * q + 2] = fmaf(w[cc], mv.z, acc[4 * q + 2]);
