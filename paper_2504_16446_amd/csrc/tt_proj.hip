@@ -593,7 +593,8 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
     const int ix = bx * 4 + wave, iy = by * 8 + (lane >> 3), iz = bz * 8 + (lane & 7);
     const bool valid = ix < nx && iy < ny && iz < nz;
     const double xv[3] = {ix - 0.5 * (nx - 1), iy - 0.5 * (ny - 1), iz - 0.5 * (nz - 1)};
-    const double dstep = (double)step, inv_step = 1.0 / dstep;
+    const double inv_step = 1.0 / (double)step;
+    const float stepf = step, inv_stepf = (float)inv_step;
 
     f4 acc[MT][4];
 #pragma unroll
@@ -608,25 +609,36 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
 #pragma unroll
         for (int u = 0; u < UP; ++u) q[u] = 0.0f;
         if (valid) {
-            // voxel centre in the ray frame (float64: magnitudes up to the volume size)
+            // Voxel centre in the ray frame: detector coordinates (a, bb) and
+            // the along-ray coordinate t / step, in float64 (magnitudes up to
+            // the volume size), each split into an integer and a fraction in
+            // [0, 1) so that every offset below is a small float32 number.
             const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
             const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
             const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
-            const double t = w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2];
+            const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
+            const double af = floor(a), bf = floor(bb), tf = floor(ts);
+            const int ai = (int)af, bi = (int)bf, ti = (int)tf;
+            const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
             const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
-            const int jlo = max(0, (int)ceil(a - f.lj)), jhi = min(nj - 1, (int)floor(a + f.lj));
+            const float ljf = (float)f.lj;
+            const int jlo = max(0, ai + (int)ceilf(ar - ljf)), jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
             for (int j = jlo; j <= jhi; ++j) {
-                // rays of this row that can meet the open cube around the voxel (float32 offsets < 2)
-                const float dj = (float)(j - a);
+                // rays of this row that can meet the open cube around the voxel
+                const float dj = (float)(j - ai) - ar;
                 const float zmax = fminf(fminf(fmaf(f.hull[0], dj, f.hull[1]), fmaf(f.hull[2], dj, f.hull[3])),
                                          fmaf(f.hull[4], dj, f.hull[5]));
                 const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, f.hull[7]), fmaf(f.hull[8], dj, f.hull[9])),
                                          fmaf(f.hull[10], dj, f.hull[11]));
-                const int klo = max(0, (int)ceil(bb + (double)zmin - 1e-4));
-                const int khi = min(nk - 1, (int)floor(bb + (double)zmax + 1e-4));
+                const int klo = max(0, bi + (int)ceilf(br + zmin - 1e-4f));
+                const int khi = min(nk - 1, bi + (int)floorf(br + zmax + 1e-4f));
                 const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
+                const f4 *yrow = reinterpret_cast<const f4 *>(yf + ((long long)s * nj + j) * nk * UP);
                 for (int k = klo; k <= khi; ++k) {
-                    const float dk = (float)(k - bb);
+                    f4 yv[UP / 4];
+#pragma unroll
+                    for (int u4 = 0; u4 < UP / 4; ++u4) yv[u4] = yrow[k * (UP / 4) + u4];  // in flight meanwhile
+                    const float dk = (float)(k - bi) - br;
                     const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
                     // parameter range along the ray inside the open cube: |P_m + tau d_m| < 1 for every axis
                     float tlo = -3.0e38f, thi = 3.0e38f;
@@ -640,34 +652,34 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
                             thi = -3.0e38f;
                         }
                     }
-                    if (!(tlo < thi)) continue;
-                    const int n0 = (int)ceil((t + (double)tlo) * inv_step), n1 = (int)floor((t + (double)thi) * inv_step);
-                    if (n0 > n1) continue;
-                    float tau = (float)(n0 * dstep - t);
-                    const float stepf = (float)dstep;
                     float wsum = 0.0f;
-                    for (int n = n0; n <= n1; ++n) {
-                        const float wx = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[0], P[0])));
-                        const float wy = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[1], P[1])));
-                        const float wz = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[2], P[2])));
-                        wsum = fmaf(wx * wy, wz, wsum);
-                        tau += stepf;
+                    if (tlo < thi) {
+                        // samples n with tau = n step - t inside (tlo, thi)
+                        const int m0 = (int)ceilf(tr + tlo * inv_stepf), m1 = (int)floorf(tr + thi * inv_stepf);
+                        float tau = ((float)m0 - tr) * stepf;
+                        for (int mm = m0; mm <= m1; ++mm) {
+                            const float wx = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[0], P[0])));
+                            const float wy = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[1], P[1])));
+                            const float wz = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[2], P[2])));
+                            wsum = fmaf(wx * wy, wz, wsum);
+                            tau += stepf;
+                        }
                     }
-                    const f4 *yp = reinterpret_cast<const f4 *>(yf + (((long long)s * nj + j) * nk + k) * UP);
 #pragma unroll
                     for (int u4 = 0; u4 < UP; u4 += 4) {
-                        f4 yv = yp[u4 / 4];
-                        q[u4 + 0] = fmaf(wsum, yv.x, q[u4 + 0]);
-                        q[u4 + 1] = fmaf(wsum, yv.y, q[u4 + 1]);
-                        q[u4 + 2] = fmaf(wsum, yv.z, q[u4 + 2]);
-                        q[u4 + 3] = fmaf(wsum, yv.w, q[u4 + 3]);
+                        q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
+                        q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
+                        q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
+                        q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
                     }
                 }
             }
         }
 #pragma unroll
         for (int u = 0; u < UP; ++u) Qw[lane * (UP + 1) + u] = q[u];
-        __syncthreads();
+        // Qw is private to this wave, whose LDS accesses complete in program
+        // order: only compiler reordering has to be fenced.
+        __builtin_amdgcn_wave_barrier();
         // g tile += B_s^T (coefficients x u) * Q^T (u x voxels)
         if constexpr (BF16) {
             // K = 16 (u padded with zeros): A from BuT16[s][coefficient][u], B = Q rounded to bf16
@@ -701,7 +713,7 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
                 }
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 
     // epilogue: lane holds rows (coefficients) 16 mt + 4 (lane/16) + r of voxel column 16 nt + lane % 16
