@@ -125,10 +125,126 @@ __global__ __launch_bounds__(256) void k_map_fp32(const float *__restrict__ c, c
     }
 }
 
+// Register-resident variant for Cp <= 64 (ell_max <= 12): each wave keeps
+// its B operands for every k-step in registers, and the block walks voxel
+// tiles with a stride of the grid, prefetching the next tile's coefficients
+// into registers while the current tile's MFMAs run, so coefficient loads,
+// MFMAs and the M stores of consecutive tiles overlap.
+constexpr int kCtStrideRb = 81;  // odd: the transposed tile writes hit distinct banks
+
+template <int UP, int KS>
+__global__ __launch_bounds__(256) void k_map_fp32_rb(const float *__restrict__ c, const float *__restrict__ Bsw,
+                                                     int V, int C, int ny, int nz, int s0, int np,
+                                                     long long vol_pad, float *__restrict__ M)
+{
+    constexpr int Cp = 4 * KS;
+    constexpr int NPF = (16 * Cp + 255) / 256;  // float4 per thread covering a 64 x C tile (C <= Cp)
+    __shared__ float cT[Cp * kCtStrideRb];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kq = lane >> 4;
+    const int rt0 = (s0 * UP) / 16 + blockIdx.y * 16 + wave * 4;
+    float a[4][KS];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a[mt][ks] = Bsw[((long long)(rt0 + mt) * KS + ks) * 64 + lane];
+    // padding coefficients C..Cp-1 stay zero for every tile
+    for (int e = tid; e < (Cp - C) * 64; e += 256) cT[(C + e / 64) * kCtStrideRb + (e & 63)] = 0.0f;
+    const int ntiles = (V + 63) / 64;
+    const int n4 = 16 * C;  // float4 in a full tile
+    const float invC = 1.0f / (float)C;
+    f4 pf[NPF];
+    auto prefetch = [&](int t) {
+        const int nvals = min(64, V - t * 64) * C;
+        const f4 *src = reinterpret_cast<const f4 *>(c + (long long)t * 64 * C);  // 256 C bytes per tile: aligned
+        const float *srcf = c + (long long)t * 64 * C;
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int e4 = tid + 256 * i;
+            pf[i] = f4{0.f, 0.f, 0.f, 0.f};
+            if (4 * e4 + 3 < nvals) {
+                pf[i] = src[e4];
+            } else if (4 * e4 < nvals) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * e4 + q < nvals) pf[i][q] = srcf[4 * e4 + q];
+            }
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) prefetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int e4 = tid + 256 * i;
+            if (e4 < n4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * e4 + q;
+                    const int v = (int)(((float)e + 0.5f) * invC);
+                    cT[(e - v * C) * kCtStrideRb + v] = pf[i][q];
+                }
+            }
+        }
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) prefetch(tile + gridDim.x);  // in flight during the MFMAs
+        f4 acc[4][4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float b = cT[(ks * 4 + kq) * kCtStrideRb + nt * 16 + (lane & 15)];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma16x16x4(a[mt][ks], b, acc[nt][mt]);
+            }
+        }
+        const int v0 = tile * 64;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int v = v0 + nt * 16 + (lane & 15);
+            if (v >= V) continue;
+            const long long vp = pad_index(v, ny, nz);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int row = blockIdx.y * 256 + wave * 64 + mt * 16 + 4 * kq;  // within the batch
+                const int p = row / UP, u0 = row % UP;
+                if (p < np) *reinterpret_cast<f4 *>(M + (long long)p * vol_pad * UP + vp * UP + u0) = acc[nt][mt];
+            }
+        }
+    }
+}
+
+template <int UP, int KS>
+static hipError_t map_fp32_rb_t(const Dims &d, const float *c, const float *Bsw, int s0, int np, float *M,
+                                hipStream_t st)
+{
+    const int V = d.nx * d.ny * d.nz;
+    const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
+    const int gy = (np * UP + 255) / 256, ntiles = (V + 63) / 64;
+    // about eight resident blocks' worth of work per CU over all row groups
+    const int gx = std::max(1, std::min(ntiles, 2048 / gy));
+    hipLaunchKernelGGL((k_map_fp32_rb<UP, KS>), dim3(gx, gy), dim3(256), 0, st, c, Bsw, V, d.C, d.ny, d.nz, s0, np,
+                       vol_pad, M);
+    return hipGetLastError();
+}
+
 template <int UP>
 static hipError_t map_fp32_t(const Dims &d, const float *c, const float *Bsw, int s0, int np, float *M,
                              hipStream_t st)
 {
+    const bool aligned = reinterpret_cast<uintptr_t>(c) % 16 == 0;  // float4 tile loads
+    switch (aligned ? d.Cp : 0) {
+    case 16: return map_fp32_rb_t<UP, 4>(d, c, Bsw, s0, np, M, st);
+    case 32: return map_fp32_rb_t<UP, 8>(d, c, Bsw, s0, np, M, st);
+    case 48: return map_fp32_rb_t<UP, 12>(d, c, Bsw, s0, np, M, st);
+    case 64: return map_fp32_rb_t<UP, 16>(d, c, Bsw, s0, np, M, st);
+    default: break;  // larger orders: B operands streamed from memory
+    }
     const int V = d.nx * d.ny * d.nz;
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     dim3 grid((V + 63) / 64, (np * UP + 255) / 256);
