@@ -193,6 +193,35 @@ def precision_report(dev, n_rays=128, n_vox=16):
     return out
 
 
+def properties_bench(dev, reps=5):
+    """Derived per-voxel quantities on a 256^3 / ell_max 8 coefficient volume:
+    HBM throughput (read C floats, write 22 floats per voxel) of one launch."""
+    import torch
+    from paper_2504_16446_amd import synth
+    from paper_2504_16446_amd.projector import PROPERTY_FIELDS, tensor_properties
+
+    w = synth.WORKLOADS["c5"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4321)
+    c = torch.randn((w.n_vox, w.n_coeff), device=dev, generator=gen)
+    out = tensor_properties(c, w.ell_max)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        tensor_properties(c, w.ell_max, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 4.0 * w.n_vox * (w.n_coeff + len(PROPERTY_FIELDS))
+    del c, out
+    torch.cuda.empty_cache()
+    return {"workload": f"{w.n[0]}^3 voxels x {w.n_coeff} coefficients (ell_max {w.ell_max})",
+            "ms": ms, "algorithmic_bytes": nbytes, "achieved": nbytes / (ms * 1e-3) / 1e9,
+            "unit": "GB/s", "peak": HBM_PEAK_GBPS, "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +349,8 @@ def main():
             ttr["warm_start_c5"] = warmstart.compare(model, synth.WORKLOADS["c5"], 1e-3, 1500)
     print("[bench] precision report ...", file=sys.stderr, flush=True)
     precision = None if args.no_precision else precision_report(dev)
+    print("[bench] derived quantities ...", file=sys.stderr, flush=True)
+    props = None if args.no_precision else properties_bench(dev)
 
     line = {
         "metric": "fwd+adj projector GB/s & % HBM roof; time-to-residual warm-start vs plain",
@@ -335,6 +366,7 @@ def main():
         "kernels": kernels,
         "time_to_residual": ttr,
         "precision": precision,
+        "tensor_properties": props,
     }
     print(json.dumps(line), flush=True)
 
