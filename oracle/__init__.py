@@ -53,7 +53,7 @@ class Geom(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("ell_max", C.c_int32), ("n_proj", C.c_int32),
         ("nj", C.c_int32), ("nk", C.c_int32), ("n_seg", C.c_int32), ("n_sub", C.c_int32),
-        ("reserved", C.c_int32),
+        ("model", C.c_int32),
         ("step", C.c_double), ("seg_span", C.c_double),
         ("inner", _dp), ("outer", _dp), ("joff", _dp), ("koff", _dp),
         ("p", C.c_double * 3), ("j", C.c_double * 3), ("k", C.c_double * 3),
@@ -105,7 +105,7 @@ class Geometry:
     """Acquisition geometry; keeps the angle arrays alive for the C struct."""
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame, n_sub=3, step=1.0,
-                 seg_span=2 * np.pi, joff=None, koff=None):
+                 seg_span=2 * np.pi, joff=None, koff=None, model="trilinear"):
         self.n = tuple(int(v) for v in n)
         self.ell_max = int(ell_max)
         self.inner = _f64(inner)
@@ -115,7 +115,11 @@ class Geometry:
         self.nj, self.nk, self.n_seg, self.n_sub = int(nj), int(nk), int(n_seg), int(n_sub)
         self.step, self.seg_span = float(step), float(seg_span)
         self.frame = {k: tuple(float(x) for x in v) for k, v in frame.items()}
+        if model not in ("trilinear", "joseph"):
+            raise ValueError("model must be 'trilinear' or 'joseph'")
+        self.model = model
         g = Geom()
+        g.model = 1 if model == "joseph" else 0
         g.nx, g.ny, g.nz = self.n
         g.ell_max = self.ell_max
         g.n_proj = len(self.inner)

@@ -32,6 +32,10 @@
  *   - small-angle scattering direction q(phi) = cos(phi) q0 + sin(phi) q90
  *     (the approximate form of Eq. 1).
  *   - loss L(c) = sum w (Ac - I)^2 + mu sum c^2, no 1/2, no normalisation.
+ *   - with model = 1, P_{sjk,xyz} is Joseph's method instead (the paper's own
+ *     projector, sect. 3.5): cuts with the voxel-centre planes normal to the
+ *     ray's dominant axis A (ties within 1e-9 go to the lower axis), bilinear
+ *     interpolation within each plane, weight 1/|d_A| per cut.
  *
  * Parity status: every function here is pinned by the CPU test-suite (closed
  * forms, invariants, library special cases, brute force); none is unpinned.
@@ -51,7 +55,7 @@ typedef struct {
     int32_t ell_max;
     int32_t n_proj;
     int32_t nj, nk, n_seg, n_sub;
-    int32_t reserved;
+    int32_t model;        /* 0: unit-step trilinear samples; 1: Joseph's method */
     double step;          /* ray sample spacing, in voxels */
     double seg_span;      /* angular range covered by the segments (2 pi) */
     const double *inner;  /* alpha_s, radians, length n_proj */
@@ -266,6 +270,117 @@ static void og_ray_sum(const og_geom *g, const og_frame *f, int j, int k, const 
     for (int i = 0; i < C; ++i) J[i] *= g->step;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Joseph's method (the discretisation the paper's projector uses, sect.     */
+/* 3.5): the ray is cut by every voxel-centre plane normal to its dominant   */
+/* axis A; at each cut the field is interpolated bilinearly in the two other */
+/* axes (zero outside the volume), and each cut is weighted by the path      */
+/* length between consecutive planes, 1 / |d_A|.                             */
+/* ------------------------------------------------------------------------ */
+
+/* Dominant axis of d; ties (within 1e-9) go to the lower axis index. */
+static int og_dominant_axis(const double *d)
+{
+    int a = 0;
+    for (int q = 1; q < 3; ++q)
+        if (fabs(d[q]) > fabs(d[a]) + 1e-9) a = q;
+    return a;
+}
+
+static void og_dims(const og_geom *g, int *n)
+{
+    n[0] = g->nx;
+    n[1] = g->ny;
+    n[2] = g->nz;
+}
+
+/* Cut of ray (j, k) with the centre plane of voxel layer i along axis A:
+ * returns the in-plane coordinates u[3] (voxel index units, u[A] = i). */
+static void og_joseph_cut(const og_geom *g, const og_frame *f, int A, int j, int k, int i, double *u)
+{
+    int n[3];
+    og_dims(g, n);
+    double base[3];
+    for (int q = 0; q < 3; ++q) base[q] = f->o[q] + j * f->ej[q] + k * f->ek[q];
+    double xA = i - 0.5 * (n[A] - 1);           /* centred coordinate of the plane */
+    double t = (xA - base[A]) / f->d[A];
+    for (int q = 0; q < 3; ++q) u[q] = base[q] + t * f->d[q] + 0.5 * (n[q] - 1);
+    u[A] = i;
+}
+
+/* J_i = (1 / |d_A|) sum over layers of the bilinear interpolation of c_i. */
+static void og_ray_sum_joseph(const og_geom *g, const og_frame *f, int j, int k, const double *c, int C,
+                              double *J)
+{
+    int n[3];
+    og_dims(g, n);
+    int A = og_dominant_axis(f->d), B = (A + 1) % 3, Cx = (A + 2) % 3;
+    for (int q = 0; q < C; ++q) J[q] = 0.0;
+    for (int i = 0; i < n[A]; ++i) {
+        double u[3];
+        og_joseph_cut(g, f, A, j, k, i, u);
+        int b0 = (int)floor(u[B]), c0 = (int)floor(u[Cx]);
+        for (int bb = b0; bb <= b0 + 1; ++bb) {
+            if (bb < 0 || bb >= n[B]) continue;
+            double wb = 1.0 - fabs(u[B] - bb);
+            for (int cc = c0; cc <= c0 + 1; ++cc) {
+                if (cc < 0 || cc >= n[Cx]) continue;
+                double w = wb * (1.0 - fabs(u[Cx] - cc));
+                if (w <= 0.0) continue;
+                int v[3];
+                v[A] = i;
+                v[B] = bb;
+                v[Cx] = cc;
+                const double *cv = c + (((int64_t)v[0] * g->ny + v[1]) * g->nz + v[2]) * C;
+                for (int q = 0; q < C; ++q) J[q] += w * cv[q];
+            }
+        }
+    }
+    for (int q = 0; q < C; ++q) J[q] /= fabs(f->d[A]);
+}
+
+/* Transpose of og_ray_sum_joseph: add (w / |d_A|) ybar to the interpolated voxels. */
+static void og_ray_splat_joseph(const og_geom *g, const og_frame *f, int j, int k, const double *ybar, int C,
+                                double *acc)
+{
+    int n[3];
+    og_dims(g, n);
+    int A = og_dominant_axis(f->d), B = (A + 1) % 3, Cx = (A + 2) % 3;
+    double inv = 1.0 / fabs(f->d[A]);
+    for (int i = 0; i < n[A]; ++i) {
+        double u[3];
+        og_joseph_cut(g, f, A, j, k, i, u);
+        int b0 = (int)floor(u[B]), c0 = (int)floor(u[Cx]);
+        for (int bb = b0; bb <= b0 + 1; ++bb) {
+            if (bb < 0 || bb >= n[B]) continue;
+            double wb = 1.0 - fabs(u[B] - bb);
+            for (int cc = c0; cc <= c0 + 1; ++cc) {
+                if (cc < 0 || cc >= n[Cx]) continue;
+                double w = wb * (1.0 - fabs(u[Cx] - cc));
+                if (w <= 0.0) continue;
+                int v[3];
+                v[A] = i;
+                v[B] = bb;
+                v[Cx] = cc;
+                double *av = acc + (((int64_t)v[0] * g->ny + v[1]) * g->nz + v[2]) * C;
+                for (int q = 0; q < C; ++q) av[q] += w * inv * ybar[q];
+            }
+        }
+    }
+}
+
+/* Joseph weight of voxel v for ray (j, k): (1/|d_A|) times the bilinear
+ * weight of v at the ray's cut with v's own layer along A. */
+static double og_joseph_weight(const og_geom *g, const og_frame *f, int j, int k, const int *v)
+{
+    int A = og_dominant_axis(f->d), B = (A + 1) % 3, Cx = (A + 2) % 3;
+    double u[3];
+    og_joseph_cut(g, f, A, j, k, v[A], u);
+    double db = fabs(u[B] - v[B]), dc = fabs(u[Cx] - v[Cx]);
+    if (db >= 1.0 || dc >= 1.0) return 0.0;
+    return (1.0 - db) * (1.0 - dc) / fabs(f->d[A]);
+}
+
 /* Forward model (Eq. forward_model): I[s][j][k][c] = sum_i B[s][c][i] J_i. */
 void og_project(const og_geom *g, const double *B, const double *c, double *I)
 {
@@ -278,7 +393,10 @@ void og_project(const og_geom *g, const double *B, const double *c, double *I)
         og_get_frame(g, s, &f);
         double *J = (double *)malloc(sizeof(double) * C);
         for (int k = 0; k < g->nk; ++k) {
-            og_ray_sum(g, &f, j, k, c, C, J);
+            if (g->model == 1)
+                og_ray_sum_joseph(g, &f, j, k, c, C, J);
+            else
+                og_ray_sum(g, &f, j, k, c, C, J);
             double *out = I + (((int64_t)s * g->nj + j) * g->nk + k) * g->n_seg;
             for (int cc = 0; cc < g->n_seg; ++cc) {
                 const double *b = B + ((int64_t)s * g->n_seg + cc) * C;
@@ -302,7 +420,10 @@ void og_project_rays(const og_geom *g, const double *B, const double *c, int64_t
         og_frame f;
         og_get_frame(g, s, &f);
         double *J = (double *)malloc(sizeof(double) * C);
-        og_ray_sum(g, &f, j, k, c, C, J);
+        if (g->model == 1)
+            og_ray_sum_joseph(g, &f, j, k, c, C, J);
+        else
+            og_ray_sum(g, &f, j, k, c, C, J);
         for (int cc = 0; cc < g->n_seg; ++cc) {
             const double *b = B + ((int64_t)s * g->n_seg + cc) * C;
             double v = 0.0;
@@ -380,7 +501,10 @@ void og_adjoint(const og_geom *g, const double *B, const double *y, double *out,
                     for (int cc = 0; cc < g->n_seg; ++cc) v += B[((int64_t)s * g->n_seg + cc) * C + i] * yr[cc];
                     ybar[i] = v;
                 }
-                og_ray_splat(g, &f, j, k, ybar, C, priv[tid]);
+                if (g->model == 1)
+                    og_ray_splat_joseph(g, &f, j, k, ybar, C, priv[tid]);
+                else
+                    og_ray_splat(g, &f, j, k, ybar, C, priv[tid]);
             }
         }
         free(ybar);
@@ -413,6 +537,25 @@ void og_adjoint_voxels(const og_geom *g, const double *B, const double *y, int64
             double a = w[0] * f.ej[0] + w[1] * f.ej[1] + w[2] * f.ej[2];
             double b = w[0] * f.ek[0] + w[1] * f.ek[1] + w[2] * f.ek[2];
             double t = w[0] * f.d[0] + w[1] * f.d[1] + w[2] * f.d[2];
+            if (g->model == 1) {
+                /* every pixel within 4 of the voxel's detector position */
+                const int vv[3] = {ix, iy, iz};
+                for (int j = (int)floor(a) - 4; j <= (int)floor(a) + 5; ++j) {
+                    if (j < 0 || j >= g->nj) continue;
+                    for (int k = (int)floor(b) - 4; k <= (int)floor(b) + 5; ++k) {
+                        if (k < 0 || k >= g->nk) continue;
+                        double wj = og_joseph_weight(g, &f, j, k, vv);
+                        if (wj == 0.0) continue;
+                        const double *yr = y + (((int64_t)s * g->nj + j) * g->nk + k) * g->n_seg;
+                        for (int i = 0; i < C; ++i) {
+                            double v2 = 0.0;
+                            for (int cc = 0; cc < g->n_seg; ++cc) v2 += B[((int64_t)s * g->n_seg + cc) * C + i] * yr[cc];
+                            o[i] += wj * v2;
+                        }
+                    }
+                }
+                continue;
+            }
             int j0 = (int)floor(a) - 2, k0 = (int)floor(b) - 2;
             int n0 = (int)floor((t - 2.0) / g->step) - 1, n1 = (int)ceil((t + 2.0) / g->step) + 1;
             for (int j = j0; j <= j0 + 5; ++j) {
@@ -451,7 +594,10 @@ void og_splat_projection(const og_geom *g, int s, const double *yf, int nu, doub
     memset(Q, 0, sizeof(double) * nv);
     for (int j = 0; j < g->nj; ++j)
         for (int k = 0; k < g->nk; ++k)
-            og_ray_splat(g, &f, j, k, yf + ((int64_t)j * g->nk + k) * nu, nu, Q);
+            if (g->model == 1)
+                og_ray_splat_joseph(g, &f, j, k, yf + ((int64_t)j * g->nk + k) * nu, nu, Q);
+            else
+                og_ray_splat(g, &f, j, k, yf + ((int64_t)j * g->nk + k) * nu, nu, Q);
 }
 
 /* ------------------------------------------------------------------------ */
