@@ -97,6 +97,21 @@ int tt_set_stream(tt_ctx *ctx, void *hip_stream);
 /* Select TT_MAP_FP32 or TT_MAP_BF16 for tt_project / tt_adjoint. */
 int tt_set_map_precision(tt_ctx *ctx, int precision);
 
+/* Discretisation of the projection operator P_{sjk,xyz} (Eq. projection_operator):
+ *   TT_PROJ_TRILINEAR (default): samples every `step` voxels along the ray,
+ *     trilinear (tent) weights, each sample weighted by `step`;
+ *   TT_PROJ_JOSEPH: Joseph's method, the paper's own projector (sect. 3.5):
+ *     the ray is cut by every voxel-centre plane normal to its dominant axis A
+ *     (ties within 1e-9 go to the lower axis), the field is interpolated
+ *     bilinearly in the two other axes at each cut, and each cut is weighted
+ *     by 1/|d_A|; `step` is not used.
+ * tt_project, tt_adjoint, tt_loss_grad and the solver use the selection made
+ * before they are called (exact transposes of each other in both models).
+ * TT_EINVAL for another value. */
+#define TT_PROJ_TRILINEAR 0
+#define TT_PROJ_JOSEPH 1
+int tt_set_projector(tt_ctx *ctx, int model);
+
 /* Number of real even-order SH coefficients up to ell_max (or TT_EINVAL). */
 int tt_num_coeffs(int ell_max);
 

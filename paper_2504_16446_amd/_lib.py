@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtt_hip.so")
 
 TT_MAP_FP32, TT_MAP_BF16 = 0, 1
+TT_PROJ_TRILINEAR, TT_PROJ_JOSEPH = 0, 1
 KERNEL_CLASSES = ["map", "march", "fold", "backproject", "residual", "vector", "plan"]
 _ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EUNSUPPORTED"}
 
@@ -49,6 +50,7 @@ _SIGS = [
     ("tt_destroy", None, [_vp]),
     ("tt_set_stream", C.c_int, [_vp, _vp]),
     ("tt_set_map_precision", C.c_int, [_vp, C.c_int]),
+    ("tt_set_projector", C.c_int, [_vp, C.c_int]),
     ("tt_num_coeffs", C.c_int, [C.c_int]),
     ("tt_sizes", C.c_int, [_vp, C.POINTER(C.c_int64)]),
     ("tt_basis_matrix", C.c_int, [_vp, C.POINTER(C.c_double)]),

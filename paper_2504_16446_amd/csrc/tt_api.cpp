@@ -233,6 +233,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     d.Cp = round_up(d.C, 16);
     d.S = g.n_proj; d.nj = g.nj; d.nk = g.nk; d.nseg = g.n_seg;
     d.step = (float)g.step;
+    d.joseph = 0;
     // Even orders: Y(-q) = Y(q), and with segments over the full circle segment
     // c + n_seg/2 probes exactly the antipodes of segment c.
     const bool antipodal = std::fabs(g.seg_span - 2.0 * M_PI) < 1e-12 && g.n_seg % 2 == 0;
@@ -340,6 +341,17 @@ int tt_set_stream(tt_ctx *c, void *stream)
 {
     if (!c) return fail(TT_EINVAL, "ctx is null");
     c->stream = (hipStream_t)stream;
+    return TT_OK;
+}
+
+int tt_set_projector(tt_ctx *c, int model)
+{
+    if (!c) return fail(TT_EINVAL, "null context");
+    if (model != TT_PROJ_TRILINEAR && model != TT_PROJ_JOSEPH)
+        return fail(TT_EINVAL, "model must be TT_PROJ_TRILINEAR or TT_PROJ_JOSEPH");
+    c->d.joseph = model == TT_PROJ_JOSEPH;
+    // Joseph's cuts carry their own 1/|d_A| weight: no sample-spacing factor
+    c->d.step = c->d.joseph ? 1.0f : (float)c->g.step;
     return TT_OK;
 }
 

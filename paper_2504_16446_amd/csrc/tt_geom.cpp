@@ -173,6 +173,23 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
         f.lk = std::fabs(f.ek[0]) + std::fabs(f.ek[1]) + std::fabs(f.ek[2]);
         for (int a = 0; a < 3; ++a) f.inv_d[a] = std::fabs(f.d[a]) > 1e-12 ? 1.0 / f.d[a] : 0.0;
         cube_shadow(f.ej, f.ek, f.hull);
+        {
+            int A = 0;
+            for (int q = 1; q < 3; ++q)
+                if (std::fabs(f.d[q]) > std::fabs(f.d[A]) + 1e-9) A = q;
+            const int B = (A + 1) % 3, C2 = (A + 2) % 3;
+            const double rj = f.ej[A] / f.d[A], rk = f.ek[A] / f.d[A];
+            const double gjB = f.ej[B] - rj * f.d[B], gjC = f.ej[C2] - rj * f.d[C2];
+            const double gkB = f.ek[B] - rk * f.d[B], gkC = f.ek[C2] - rk * f.d[C2];
+            const double det = gjB * gkC - gkB * gjC;  // +-1/|d_A| for an orthonormal frame
+            f.jos_a = A;
+            f.jos_w = (float)(1.0 / std::fabs(f.d[A]));
+            f.jos_gj[0] = (float)gjB;
+            f.jos_gj[1] = (float)gjC;
+            f.jos_gk[0] = (float)gkB;
+            f.jos_gk[1] = (float)gkC;
+            f.jos_rj = (float)((std::fabs(gkB) + std::fabs(gkC)) / std::fabs(det));
+        }
         for (int a = 0; a < 3; ++a) {
             f.ejf[a] = (float)f.ej[a];
             f.ekf[a] = (float)f.ek[a];

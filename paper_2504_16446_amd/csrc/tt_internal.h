@@ -40,6 +40,16 @@ struct ProjFrame {
     // voxels that contains every corner those samples touch.  slab_w = 0:
     // the projection's rays gather from global memory instead.
     int slab_a, slab_w, slab_eb, slab_ez;
+    // Joseph's method: dominant axis A of d (ties within 1e-9 go to the lower
+    // axis) and the cut weight 1/|d_A|; for the adjoint, the in-plane offset of
+    // a ray's cut from a voxel centre in the voxel's layer is
+    // Delta_{B,C} = dj * jos_gj + dk * jos_gk (B = (A+1)%3, C = (A+2)%3) for
+    // detector offsets (dj, dk) from the voxel's own position, and the
+    // support |Delta_B|, |Delta_C| < 1 needs |dj| < jos_rj.
+    int jos_a;
+    float jos_w;
+    float jos_gj[2], jos_gk[2];
+    float jos_rj;
 };
 
 constexpr int kMarchTile = 16;  // rays per tile edge in the forward march
@@ -59,8 +69,9 @@ struct Dims {
     int C, Cp;          // coefficients, padded to a multiple of 16
     int S, nj, nk;      // projections and detector
     int nseg, U, Up;    // segments, unique segments, padded unique segments
-    float step;
+    float step;         // sample spacing of the trilinear model (1 for Joseph: no step factor)
     int march_lds;      // dynamic LDS bytes of the staged march (0: no projection staged)
+    int joseph;         // 0: unit-step trilinear samples, 1: Joseph's method
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).

@@ -572,12 +572,95 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
     }
 }
 
+// ---------------------------------------------------------------------------
+// Joseph's method forward (the paper's own projector, sect. 3.5): one thread
+// per ray; the ray is cut by every voxel-centre plane normal to its dominant
+// axis A, the field interpolated bilinearly from M in the two other axes at
+// each cut (zero border), and each cut weighted by 1/|d_A|.  Planes are in
+// padded index coordinates P = layer + 1; cuts whose in-plane coordinates
+// leave (0, n + 1) touch only the zero border and are skipped.
+// ---------------------------------------------------------------------------
+template <int UP>
+__global__ __launch_bounds__(256) void k_march_joseph(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
+                                                      int s0, int nx, int ny, int nz, int nj, int nk, int nseg,
+                                                      int U, long long vol_pad, float *__restrict__ I)
+{
+    const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
+    const int lb = blockIdx.x;
+    const int p = lb / (ntj * ntk), s = s0 + p;
+    const int tj = (lb / ntk) % ntj, tk = lb % ntk;
+    const int j = tj * kMarchTile + (threadIdx.x % kMarchTile);
+    const int k = tk * kMarchTile + (threadIdx.x / kMarchTile);
+    if (j >= nj || k >= nk) return;  // no block-level synchronisation below
+    const ProjFrame &f = frames[s];
+    const int A = f.jos_a, B = (A + 1) % 3, Cc = (A + 2) % 3;
+    const int n3[3] = {nx, ny, nz};
+    double b[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) b[a] = f.o[a] + j * f.ej[a] + k * f.ek[a] + 0.5 * (n3[a] + 1.0);
+    const double rB = f.d[B] * f.inv_d[A], rC = f.d[Cc] * f.inv_d[A];
+    // planes P in [1, n_A] whose cut lies inside (0, n + 1) along B and C
+    double plo = 1.0, phi = (double)n3[A];
+    const double rq[2] = {rB, rC};
+    const int qq[2] = {B, Cc};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int q = qq[i];
+        if (rq[i] != 0.0) {
+            const double t1 = b[A] - b[q] / rq[i], t2 = b[A] + ((double)n3[q] + 1.0 - b[q]) / rq[i];
+            plo = fmax(plo, fmin(t1, t2));
+            phi = fmin(phi, fmax(t1, t2));
+        } else if (!(b[q] > 0.0 && b[q] < (double)n3[q] + 1.0)) {
+            phi = -1.0;
+        }
+    }
+    const long long str[3] = {(long long)(ny + 2) * (nz + 2) * UP, (long long)(nz + 2) * UP, (long long)UP};
+    const long long sA = str[A], sB = str[B], sC = str[Cc];
+    const float *Mp = M + (long long)p * vol_pad * UP;
+    float acc[UP];
+#pragma unroll
+    for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
+    const int P0 = max(1, (int)ceil(plo)), P1 = min(n3[A], (int)floor(phi));
+    for (int P = P0; P <= P1; ++P) {
+        const double t = (double)P - b[A];
+        const double pB = fma(t, rB, b[B]), pC = fma(t, rC, b[Cc]);
+        const int iB = min(max((int)floor(pB), 0), n3[B]), iC = min(max((int)floor(pC), 0), n3[Cc]);
+        const float fB = (float)(pB - iB), fC = (float)(pC - iC);
+        const float w[4] = {(1.0f - fB) * (1.0f - fC), (1.0f - fB) * fC, fB * (1.0f - fC), fB * fC};
+        const float *q = Mp + P * sA + iB * sB + iC * sC;
+        const long long off[4] = {0, sC, sB, sB + sC};
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+#pragma unroll
+            for (int u4 = 0; u4 < UP; u4 += 4) {
+                const f4 m = *reinterpret_cast<const f4 *>(q + off[cc] + u4);
+                acc[u4 + 0] = fmaf(w[cc], m.x, acc[u4 + 0]);
+                acc[u4 + 1] = fmaf(w[cc], m.y, acc[u4 + 1]);
+                acc[u4 + 2] = fmaf(w[cc], m.z, acc[u4 + 2]);
+                acc[u4 + 3] = fmaf(w[cc], m.w, acc[u4 + 3]);
+            }
+        }
+    }
+    float *out = I + (((long long)s * nj + j) * nk + k) * nseg;
+#pragma unroll
+    for (int u = 0; u < UP; ++u) {
+        if (u < U) {
+            for (int cseg = u; cseg < nseg; cseg += U) out[cseg] = f.jos_w * acc[u];
+        }
+    }
+}
+
 template <int UP>
 static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np, float *I,
                           hipStream_t st)
 {
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * np);
+    if (d.joseph) {
+        hipLaunchKernelGGL(k_march_joseph<UP>, grid, dim3(kMarchTile * kMarchTile), 0, st, M, frames, s0, d.nx, d.ny,
+                           d.nz, d.nj, d.nk, d.nseg, d.U, vol_pad, I);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_march<UP>, grid, dim3(kMarchTile * kMarchTile), d.march_lds, st, M, frames, s0, d.nx, d.ny,
                        d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I);
     return hipGetLastError();
@@ -693,7 +776,7 @@ hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *dat
 // backproject: block = brick of 4 (x) x 8 (y) x 8 (z) voxels; wave w owns the
 // x-slice w (64 voxels = 4 column tiles of 16).  Loops over all projections.
 // ---------------------------------------------------------------------------
-template <int UP, int MT, bool BF16>
+template <int UP, int MT, bool BF16, bool JOS>
 __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ yf, const ProjFrame *__restrict__ frames,
                                                      const float *__restrict__ Bu, const s4 *__restrict__ BuT16, int S, int nx, int ny, int nz,
                                                      int nj, int nk, int C, int Cp, float step,
@@ -724,7 +807,59 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
         float q[UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) q[u] = 0.0f;
-        if (valid) {
+        if (JOS && valid) {
+            // Joseph's method: the rays whose cut with the voxel's own layer
+            // (normal to the dominant axis) lies within one voxel along the two
+            // in-plane axes; weight (1 - |Delta_B|)(1 - |Delta_C|) / |d_A|.
+            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+            const double af = floor(a), bf = floor(bb);
+            const int ai = (int)af, bi = (int)bf;
+            const float ar = (float)(a - af), br = (float)(bb - bf);
+            const float gjB = f.jos_gj[0], gjC = f.jos_gj[1], gkB = f.jos_gk[0], gkC = f.jos_gk[1];
+            const int jlo = max(0, ai + (int)ceilf(ar - f.jos_rj)), jhi = min(nj - 1, ai + (int)floorf(ar + f.jos_rj));
+            for (int j = jlo; j <= jhi; ++j) {
+                const float dj = (float)(j - ai) - ar;
+                const float eB = dj * gjB, eC = dj * gjC;
+                float lo = -3.0e38f, hi = 3.0e38f;
+                if (fabsf(gkB) > 1e-6f) {
+                    const float x1 = (-1.0f - eB) / gkB, x2 = (1.0f - eB) / gkB;
+                    lo = fmaxf(lo, fminf(x1, x2));
+                    hi = fminf(hi, fmaxf(x1, x2));
+                } else if (fabsf(eB) >= 1.0f) {
+                    hi = -3.0e38f;
+                }
+                if (fabsf(gkC) > 1e-6f) {
+                    const float x1 = (-1.0f - eC) / gkC, x2 = (1.0f - eC) / gkC;
+                    lo = fmaxf(lo, fminf(x1, x2));
+                    hi = fminf(hi, fmaxf(x1, x2));
+                } else if (fabsf(eC) >= 1.0f) {
+                    hi = -3.0e38f;
+                }
+                if (!(lo < hi)) continue;
+                const int klo = max(0, bi + (int)ceilf(br + lo - 1e-4f));
+                const int khi = min(nk - 1, bi + (int)floorf(br + hi + 1e-4f));
+                const f4 *yrow = reinterpret_cast<const f4 *>(yf + ((long long)s * nj + j) * nk * UP);
+                for (int k = klo; k <= khi; ++k) {
+                    f4 yv[UP / 4];
+#pragma unroll
+                    for (int u4 = 0; u4 < UP / 4; ++u4) yv[u4] = yrow[k * (UP / 4) + u4];
+                    const float dk = (float)(k - bi) - br;
+                    const float wB = fmaxf(0.0f, 1.0f - fabsf(fmaf(dk, gkB, eB)));
+                    const float wC = fmaxf(0.0f, 1.0f - fabsf(fmaf(dk, gkC, eC)));
+                    const float wt = wB * wC * f.jos_w;
+#pragma unroll
+                    for (int u4 = 0; u4 < UP; u4 += 4) {
+                        q[u4 + 0] = fmaf(wt, yv[u4 / 4].x, q[u4 + 0]);
+                        q[u4 + 1] = fmaf(wt, yv[u4 / 4].y, q[u4 + 1]);
+                        q[u4 + 2] = fmaf(wt, yv[u4 / 4].z, q[u4 + 2]);
+                        q[u4 + 3] = fmaf(wt, yv[u4 / 4].w, q[u4 + 3]);
+                    }
+                }
+            }
+        }
+        if (!JOS && valid) {
             // Voxel centre in the ray frame: detector coordinates (a, bb) and
             // the along-ray coordinate t / step, in float64 (magnitudes up to
             // the volume size), each split into an integer and a fraction in
@@ -871,12 +1006,19 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
                        int bf16, float *g, float beta, const float *c, double *partials, hipStream_t st)
 {
     const s4 *bt = reinterpret_cast<const s4 *>(BuT16);
-    if (bf16)
-        hipLaunchKernelGGL((k_backproject<UP, MT, true>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames, Bu,
-                           bt, d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    const dim3 grid(backproject_blocks(d)), block(256);
+    if (bf16 && d.joseph)
+        hipLaunchKernelGGL((k_backproject<UP, MT, true, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    else if (bf16)
+        hipLaunchKernelGGL((k_backproject<UP, MT, true, false>), grid, block, 0, st, yf, frames, Bu, bt, d.S, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+    else if (d.joseph)
+        hipLaunchKernelGGL((k_backproject<UP, MT, false, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
     else
-        hipLaunchKernelGGL((k_backproject<UP, MT, false>), dim3(backproject_blocks(d)), dim3(256), 0, st, yf, frames,
-                           Bu, bt, d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+        hipLaunchKernelGGL((k_backproject<UP, MT, false, false>), grid, block, 0, st, yf, frames, Bu, bt, d.S, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
     return hipGetLastError();
 }
 

@@ -54,7 +54,8 @@ class Projector:
     """
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame=None, n_sub=3, step=1.0,
-                 seg_span=2 * math.pi, joff=None, koff=None, map_precision="fp32", device=None):
+                 seg_span=2 * math.pi, joff=None, koff=None, map_precision="fp32", device=None,
+                 model="trilinear"):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("Projector runs on a HIP device only")
@@ -81,6 +82,11 @@ class Projector:
         with torch.cuda.device(self.device):
             call("tt_create", C.byref(g), C.byref(handle))
         self._h = handle
+        if model not in ("trilinear", "joseph"):
+            raise ValueError("model must be 'trilinear' or 'joseph'")
+        call("tt_set_projector", self._h,
+             _lib.TT_PROJ_JOSEPH if model == "joseph" else _lib.TT_PROJ_TRILINEAR)
+        self.model = model
         sizes = (C.c_int64 * 6)()
         call("tt_sizes", self._h, sizes)
         self.n = tuple(int(v) for v in n)
