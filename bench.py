@@ -222,6 +222,35 @@ def properties_bench(dev, reps=5):
             "unit": "GB/s", "peak": HBM_PEAK_GBPS, "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
 
 
+def joseph_bench(w, dev, reps=3):
+    """Forward + adjoint with Joseph's method on the same workload: kernel times
+    and algorithmic GB/s (same per-projection bytes as the trilinear model)."""
+    import torch
+    from paper_2504_16446_amd.projector import Projector
+
+    P = Projector.from_workload(w, device=dev, model="joseph")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(99)
+    c = torch.randn(P.vol_shape, device=dev, generator=gen)
+    y = torch.randn(P.data_shape, device=dev, generator=gen)
+    I = P.forward(c)
+    g = P.adjoint(y)
+    torch.cuda.synchronize()
+    P.timing(True)
+    for _ in range(reps):
+        P.forward(c, out=I)
+        P.adjoint(y, out=g)
+    kt = P.timing_read()
+    P.timing(False)
+    ms = {k: v[0] / reps for k, v in kt.items() if v[1]}
+    total = sum(ms.values())
+    bytes_ = 2 * w.n_proj * algorithmic_bytes(w)
+    del P, c, y, I, g
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "ms_fwd_adj": total, "kernels_ms": ms,
+            "algorithmic_GBps": bytes_ / (total * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +380,8 @@ def main():
     precision = None if args.no_precision else precision_report(dev)
     print("[bench] derived quantities ...", file=sys.stderr, flush=True)
     props = None if args.no_precision else properties_bench(dev)
+    print("[bench] Joseph's method ...", file=sys.stderr, flush=True)
+    joseph = None if args.no_precision else joseph_bench(w, dev)
 
     line = {
         "metric": "fwd+adj projector GB/s & % HBM roof; time-to-residual warm-start vs plain",
@@ -367,6 +398,7 @@ def main():
         "time_to_residual": ttr,
         "precision": precision,
         "tensor_properties": props,
+        "joseph": joseph,
     }
     print(json.dumps(line), flush=True)
 
