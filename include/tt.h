@@ -253,6 +253,30 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
                   int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Other objectives on the same operator (sect. 3.5, "Optimization"):       */
+/* regularisers of the tensor field and fixed-step gradient descent with    */
+/* optional Nesterov momentum.  Coefficient arrays are device float         */
+/* [nx][ny][nz][C] (n = nx ny nz C elements); values accumulate in float64  */
+/* with one atomic add per block (summation order not fixed).               */
+/* ------------------------------------------------------------------------ */
+/* Laplacian regulariser lambda sum (Lap c)^2 with Lap the 7-point finite-
+ * difference Laplacian of every coefficient channel, zero outside the volume:
+ * grad += 2 lambda Lap(Lap c); value[0] += lambda sum (Lap c)^2 if value is
+ * not NULL.  work: device float [n], holds Lap c on return.  c, work and grad
+ * must not overlap. */
+int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambda, float *work, float *grad,
+                     double *value, void *stream);
+/* Huber norm lambda sum h(c_e), h(x) = x^2 / (2 delta) for |x| <= delta and
+ * |x| - delta / 2 otherwise (delta > 0): grad += lambda clamp(c / delta, -1, 1),
+ * value[0] += lambda sum h if value is not NULL. */
+int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, void *stream);
+/* One gradient step with momentum m on n floats, g = grad f(y):
+ * c_new = y - step g, y = c_new + m (c_new - c), c = c_new.  m = 0 is plain
+ * gradient descent (y then tracks c); Nesterov's schedule is m_k = (k-1)/(k+2).
+ * c, y and g must be distinct buffers. */
+int tt_gd_step(float *c, float *y, const float *g, int64_t n, float step, float momentum, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Derived per-voxel quantities (the paper's section on deriving standard    */
 /* quantities from the output: mean intensity, second-moment tensor and its  */
 /* eigendecomposition, fractional anisotropy; plus the spherical variance    */

@@ -802,6 +802,38 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
     return TT_OK;
 }
 
+int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambda, float *work, float *grad,
+                     double *value, void *stream)
+{
+    if (!c || !work || !grad) return fail(TT_EINVAL, "null pointer");
+    if (nx < 1 || ny < 1 || nz < 1 || C < 1) return fail(TT_ESHAPE, "sizes must be >= 1");
+    if ((long long)nz * C > 0x7fffffffLL || (long long)nx * ny > 0x7fffffffLL)
+        return fail(TT_EUNSUPPORTED, "volume too large");
+    if (!std::isfinite(lambda)) return fail(TT_EINVAL, "lambda must be finite");
+    TT_HIP(launch_laplacian_reg(c, nx, ny, nz, C, lambda, work, grad, value, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, void *stream)
+{
+    if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
+    if (!(delta > 0.0) || !std::isfinite(delta) || !std::isfinite(lambda)) return fail(TT_EINVAL, "bad delta or lambda");
+    if (n == 0) return TT_OK;
+    if (!c || !grad) return fail(TT_EINVAL, "null pointer");
+    TT_HIP(launch_huber_reg(c, n, delta, lambda, grad, value, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_gd_step(float *c, float *y, const float *g, int64_t n, float step, float momentum, void *stream)
+{
+    if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
+    if (!std::isfinite(step) || !std::isfinite(momentum)) return fail(TT_EINVAL, "bad step or momentum");
+    if (n == 0) return TT_OK;
+    if (!c || !y || !g) return fail(TT_EINVAL, "null pointer");
+    TT_HIP(launch_nesterov(c, y, g, n, step, momentum, (hipStream_t)stream));
+    return TT_OK;
+}
+
 int tt_tensor_properties(const float *c, int64_t n_vox, int ell_max, float *out, void *stream)
 {
     if (ell_max < 0 || ell_max % 2) return fail(TT_EINVAL, "ell_max must be even and >= 0");

@@ -101,6 +101,13 @@ int backproject_blocks(const Dims &d);
 constexpr int kPropFields = 22;
 hipError_t launch_tensor_props(const float *c, long long nvox, int C, float *out, hipStream_t st);
 
+// Regularisers and the gradient-descent update (tt_reg.hip).
+hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lam, float *work, float *grad,
+                                double *value, hipStream_t st);
+hipError_t launch_huber_reg(const float *c, long long n, double delta, double lam, float *grad, double *value,
+                            hipStream_t st);
+hipError_t launch_nesterov(float *c, float *y, const float *g, long long n, float step, float m, hipStream_t st);
+
 // Reductions: out[slot] = scale * sum of partials[0..n).
 hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,
                                int accumulate, hipStream_t st);

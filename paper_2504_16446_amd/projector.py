@@ -15,7 +15,7 @@ from . import _lib, synth
 from ._lib import Geometry, call, lib
 
 __all__ = ["Projector", "ProjectFn", "project", "LBFGS", "sh_eval", "num_coeffs", "tensor_properties",
-           "PROPERTY_FIELDS"]
+           "PROPERTY_FIELDS", "laplacian_reg", "huber_reg", "GradientDescent"]
 
 
 def num_coeffs(ell_max: int) -> int:
@@ -279,4 +279,85 @@ def tensor_properties(c: torch.Tensor, ell_max: int, out: torch.Tensor | None = 
     call("tt_tensor_properties", C.c_void_p(c.data_ptr()), n_vox, int(ell_max), C.c_void_p(out.data_ptr()),
          C.c_void_p(stream))
     return out
+
+
+def _stream(t):
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev_f32(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def laplacian_reg(c: torch.Tensor, lam: float, grad: torch.Tensor, value: torch.Tensor | None = None,
+                  work: torch.Tensor | None = None) -> torch.Tensor:
+    """grad += 2 lam Lap(Lap c); value += lam sum (Lap c)^2 (float64 device scalar).
+
+    c is (nx, ny, nz, C); returns the work tensor holding Lap c."""
+    if c.dim() != 4:
+        raise ValueError("c must be (nx, ny, nz, C)")
+    work = torch.empty_like(c) if work is None else work
+    for t, n in ((c, "c"), (grad, "grad"), (work, "work")):
+        _dev_f32(t, n)
+        if t.shape != c.shape:
+            raise ValueError(f"{n} has shape {tuple(t.shape)}, expected {tuple(c.shape)}")
+    vp = None
+    if value is not None:
+        if value.dtype != torch.float64 or not value.is_cuda:
+            raise ValueError("value must be a float64 device tensor")
+        vp = C.c_void_p(value.data_ptr())
+    nx, ny, nz, nc = (int(v) for v in c.shape)
+    call("tt_laplacian_reg", C.c_void_p(c.data_ptr()), nx, ny, nz, nc, float(lam), C.c_void_p(work.data_ptr()),
+         C.c_void_p(grad.data_ptr()), vp, _stream(c))
+    return work
+
+
+def huber_reg(c: torch.Tensor, delta: float, lam: float, grad: torch.Tensor, value: torch.Tensor | None = None):
+    """grad += lam h'(c); value += lam sum h(c), h the Huber function of width delta."""
+    _dev_f32(c, "c")
+    _dev_f32(grad, "grad")
+    if grad.shape != c.shape:
+        raise ValueError("grad and c differ in shape")
+    vp = None
+    if value is not None:
+        if value.dtype != torch.float64 or not value.is_cuda:
+            raise ValueError("value must be a float64 device tensor")
+        vp = C.c_void_p(value.data_ptr())
+    call("tt_huber_reg", C.c_void_p(c.data_ptr()), c.numel(), float(delta), float(lam), C.c_void_p(grad.data_ptr()),
+         vp, _stream(c))
+
+
+class GradientDescent:
+    """Fixed-step gradient descent, optionally with Nesterov momentum (m_k = (k-1)/(k+2)),
+    on sum w (Ac - I)^2 + mu |c|^2 + lam_lap sum (Lap c)^2 + huber_lam sum h_delta(c)."""
+
+    def __init__(self, projector: Projector, step: float, nesterov: bool = False, lam_lap: float = 0.0,
+                 huber: tuple | None = None):
+        self.P, self.step, self.nesterov = projector, float(step), bool(nesterov)
+        self.lam_lap, self.huber = float(lam_lap), huber
+
+    def objective_grad(self, c, data, w=None, mu=0.0, work=None):
+        """(value float64[1], grad) of the whole objective at c."""
+        loss, grad, _ = self.P.loss_grad(c, data, w, mu, want_resid=False)
+        if self.lam_lap:
+            laplacian_reg(c, self.lam_lap, grad, loss, work)
+        if self.huber is not None:
+            huber_reg(c, self.huber[0], self.huber[1], grad, loss)
+        return loss, grad
+
+    def run(self, c: torch.Tensor, data, w=None, mu=0.0, iters=10):
+        """Iterates in place on c; returns the objective before each step (float64, length iters)."""
+        _f32(c, self.P.vol_shape, "c", self.P.device)
+        y = c.clone()
+        work = torch.empty_like(c) if self.lam_lap else None
+        losses = torch.empty(iters, dtype=torch.float64, device=c.device)
+        for k in range(1, iters + 1):
+            val, grad = self.objective_grad(y, data, w, mu, work)
+            losses[k - 1:k].copy_(val)
+            m = (k - 1.0) / (k + 2.0) if self.nesterov else 0.0
+            call("tt_gd_step", C.c_void_p(c.data_ptr()), C.c_void_p(y.data_ptr()), C.c_void_p(grad.data_ptr()),
+                 c.numel(), self.step, m, _stream(c))
+        return losses
 

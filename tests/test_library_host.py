@@ -107,3 +107,18 @@ def test_tensor_properties_argument_errors_without_device():
     assert lib.tt_tensor_properties(p, 0, 2, p, None) == 0
     odd = C.c_void_p(C.addressof(buf) + 4)
     assert lib.tt_tensor_properties(odd, 1, 2, p, None) == -1
+
+
+def test_regulariser_argument_errors_without_device():
+    lib = _lib().lib()
+    buf = (C.c_float * 64)()
+    p = C.cast(buf, C.c_void_p)
+    assert lib.tt_laplacian_reg(None, 2, 2, 2, 1, 1.0, p, p, None, None) == -1
+    assert lib.tt_laplacian_reg(p, 0, 2, 2, 1, 1.0, p, p, None, None) == -2
+    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1, float("nan"), p, p, None, None) == -1
+    assert lib.tt_huber_reg(p, 4, 0.0, 1.0, p, None, None) == -1
+    assert lib.tt_huber_reg(p, -1, 0.1, 1.0, p, None, None) == -2
+    assert lib.tt_huber_reg(None, 0, 0.1, 1.0, None, None, None) == 0
+    assert lib.tt_gd_step(p, p, None, 4, 0.1, 0.0, None) == -1
+    assert lib.tt_gd_step(p, p, p, 4, float("inf"), 0.0, None) == -1
+    assert lib.tt_gd_step(None, None, None, 0, 0.1, 0.0, None) == 0
