@@ -222,6 +222,49 @@ def properties_bench(dev, reps=5):
             "unit": "GB/s", "peak": HBM_PEAK_GBPS, "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
 
 
+def regulariser_bench(dev, reps=5):
+    """Laplacian / Huber regularisers and the gradient-descent update on a
+    256^3 x 45 coefficient volume: HBM throughput of each (algorithmic bytes:
+    Laplacian 20 n, Huber 12 n, update 20 n for n floats)."""
+    import ctypes as C
+    import torch
+    from paper_2504_16446_amd import synth
+    from paper_2504_16446_amd._lib import call
+    from paper_2504_16446_amd.projector import huber_reg, laplacian_reg
+
+    w = synth.WORKLOADS["c5"]
+    shape = w.n + (w.n_coeff,)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    c = torch.randn(shape, device=dev, generator=gen)
+    g = torch.zeros_like(c)
+    work = torch.empty_like(c)
+    y = c.clone()
+    val = torch.zeros(1, dtype=torch.float64, device=dev)
+    n = c.numel()
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": f"{w.n[0]}^3 x {w.n_coeff} coefficients"}
+    cases = (("laplacian", 20.0, lambda: laplacian_reg(c, 1e-2, g, val, work)),
+             ("huber", 12.0, lambda: huber_reg(c, 0.05, 1e-2, g, val)),
+             ("gd_step", 20.0, lambda: call("tt_gd_step", C.c_void_p(c.data_ptr()), C.c_void_p(y.data_ptr()),
+                                            C.c_void_p(g.data_ptr()), n, 1e-6, 0.5,
+                                            C.c_void_p(stream.cuda_stream))))
+    for name, per, fn in cases:
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "GBps": per * n / (ms * 1e-3) / 1e9, "frac": per * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    del c, g, work, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def joseph_bench(w, dev, reps=3):
     """Forward + adjoint with Joseph's method on the same workload: kernel times
     and algorithmic GB/s (same per-projection bytes as the trilinear model)."""
@@ -382,6 +425,8 @@ def main():
     props = None if args.no_precision else properties_bench(dev)
     print("[bench] Joseph's method ...", file=sys.stderr, flush=True)
     joseph = None if args.no_precision else joseph_bench(w, dev)
+    print("[bench] regularisers ...", file=sys.stderr, flush=True)
+    regs = None if args.no_precision else regulariser_bench(dev)
 
     line = {
         "metric": "fwd+adj projector GB/s & % HBM roof; time-to-residual warm-start vs plain",
@@ -399,6 +444,7 @@ def main():
         "precision": precision,
         "tensor_properties": props,
         "joseph": joseph,
+        "regularisers": regs,
     }
     print(json.dumps(line), flush=True)
 

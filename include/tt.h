@@ -270,6 +270,14 @@ int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambd
  * |x| - delta / 2 otherwise (delta > 0): grad += lambda clamp(c / delta, -1, 1),
  * value[0] += lambda sum h if value is not NULL. */
 int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, void *stream);
+/* Huber loss of the residual (robust regression, the paper's HuberLoss):
+ * r = I - data, y = w clamp(r / delta, -1, 1) (pass y to tt_adjoint for the
+ * gradient A^T y), value[0] += sum w h(r) if value is not NULL.  I, data, y
+ * have n floats (data-shaped); w may be NULL (all ones). */
+int tt_huber_loss(const float *I, const float *data, const float *w, int64_t n, double delta, float *y,
+                  double *value, void *stream);
+/* value[0] += scale * sum x^2 over n floats (float64 accumulation). */
+int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *stream);
 /* One gradient step with momentum m on n floats, g = grad f(y):
  * c_new = y - step g, y = c_new + m (c_new - c), c = c_new.  m = 0 is plain
  * gradient descent (y then tracks c); Nesterov's schedule is m_k = (k-1)/(k+2).

@@ -86,6 +86,8 @@ _SIGS = [
     ("tt_laplacian_reg", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _fp, _fp, _dp, _vp]),
     ("tt_huber_reg", C.c_int, [_fp, C.c_int64, C.c_double, C.c_double, _fp, _dp, _vp]),
     ("tt_gd_step", C.c_int, [_fp, _fp, _fp, C.c_int64, C.c_float, C.c_float, _vp]),
+    ("tt_huber_loss", C.c_int, [_fp, _fp, _fp, C.c_int64, C.c_double, _fp, _dp, _vp]),
+    ("tt_sumsq", C.c_int, [_fp, C.c_int64, C.c_double, _dp, _vp]),
     ("tt_last_error", C.c_char_p, []),
     ("tt_error_string", C.c_char_p, [C.c_int]),
 ]

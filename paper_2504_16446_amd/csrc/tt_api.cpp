@@ -824,6 +824,27 @@ int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *
     return TT_OK;
 }
 
+int tt_huber_loss(const float *I, const float *data, const float *w, int64_t n, double delta, float *y,
+                  double *value, void *stream)
+{
+    if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TT_EINVAL, "delta must be > 0");
+    if (n == 0) return TT_OK;
+    if (!I || !data || !y) return fail(TT_EINVAL, "null pointer");
+    TT_HIP(launch_huber_loss(I, data, w, n, delta, y, value, (hipStream_t)stream));
+    return TT_OK;
+}
+
+int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *stream)
+{
+    if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
+    if (!value) return fail(TT_EINVAL, "null value");
+    if (n == 0) return TT_OK;
+    if (!x) return fail(TT_EINVAL, "null pointer");
+    TT_HIP(launch_sumsq(x, n, scale, value, (hipStream_t)stream));
+    return TT_OK;
+}
+
 int tt_gd_step(float *c, float *y, const float *g, int64_t n, float step, float momentum, void *stream)
 {
     if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");

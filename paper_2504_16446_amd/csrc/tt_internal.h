@@ -106,6 +106,9 @@ hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, d
                                 double *value, hipStream_t st);
 hipError_t launch_huber_reg(const float *c, long long n, double delta, double lam, float *grad, double *value,
                             hipStream_t st);
+hipError_t launch_huber_loss(const float *I, const float *data, const float *w, long long n, double delta, float *y,
+                             double *value, hipStream_t st);
+hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, hipStream_t st);
 hipError_t launch_nesterov(float *c, float *y, const float *g, long long n, float step, float m, hipStream_t st);
 
 // Reductions: out[slot] = scale * sum of partials[0..n).

@@ -27,8 +27,9 @@ __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ in,
     const float *rym = y > 0 ? r0 - row : nullptr;
     const float *ryp = y + 1 < ny ? r0 + row : nullptr;
     double ss = 0.0;
+    const float invC = 1.0f / (float)C;  // exact quotient: e < 2^22 and C <= 2^8 here
     for (int e = threadIdx.x; e < row; e += 256) {
-        const int z = e / C;
+        const int z = C <= 256 && row < (1 << 22) ? (int)(((float)e + 0.5f) * invC) : e / C;
         const float v = r0[e];
         float acc = -6.0f * v;
         if (z > 0) acc += r0[e - C];
@@ -86,6 +87,55 @@ hipError_t launch_huber_reg(const float *c, long long n, double delta, double la
     const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_huber, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, n, (float)delta, (float)lam, grad,
                        value);
+    return hipGetLastError();
+}
+
+// Huber loss on the residual r = I - data: y = w h'(r) (so that A^T y is the
+// gradient), value += sum w h(r).
+__global__ __launch_bounds__(256) void k_huber_loss(const float *__restrict__ I, const float *__restrict__ data,
+                                                    const float *__restrict__ w, long long n, float delta,
+                                                    float *__restrict__ y, double *__restrict__ value)
+{
+    __shared__ double ws[4];
+    const float inv = 1.0f / delta;
+    double hs = 0.0;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const float r = I[e] - data[e], a = fabsf(r), wt = w ? w[e] : 1.0f;
+        hs += (double)wt * (a <= delta ? 0.5 * (double)r * (double)r / (double)delta : (double)a - 0.5 * (double)delta);
+        y[e] = wt * fminf(1.0f, fmaxf(-1.0f, r * inv));
+    }
+    if (value) {
+        const double t = block_sum(hs, ws);
+        if (threadIdx.x == 0) atomicAdd(value, t);
+    }
+}
+
+hipError_t launch_huber_loss(const float *I, const float *data, const float *w, long long n, double delta, float *y,
+                             double *value, hipStream_t st)
+{
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_huber_loss, dim3(std::max(blocks, 1)), dim3(256), 0, st, I, data, w, n, (float)delta, y, value);
+    return hipGetLastError();
+}
+
+// value += scale * sum x^2 (float64)
+__global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ x, long long n, double scale,
+                                               double *__restrict__ value)
+{
+    __shared__ double ws[4];
+    double ss = 0.0;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const double v = x[e];
+        ss += v * v;
+    }
+    const double t = block_sum(ss, ws);
+    if (threadIdx.x == 0) atomicAdd(value, scale * t);
+}
+
+hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, hipStream_t st)
+{
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sumsq, dim3(std::max(blocks, 1)), dim3(256), 0, st, x, n, scale, value);
     return hipGetLastError();
 }
 

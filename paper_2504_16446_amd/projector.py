@@ -331,16 +331,34 @@ def huber_reg(c: torch.Tensor, delta: float, lam: float, grad: torch.Tensor, val
 
 class GradientDescent:
     """Fixed-step gradient descent, optionally with Nesterov momentum (m_k = (k-1)/(k+2)),
-    on sum w (Ac - I)^2 + mu |c|^2 + lam_lap sum (Lap c)^2 + huber_lam sum h_delta(c)."""
+    on sum w (Ac - I)^2 (or the Huber loss sum w h_loss_delta(Ac - I)) + mu |c|^2
+    + lam_lap sum (Lap c)^2 + huber_lam sum h_delta(c)."""
 
     def __init__(self, projector: Projector, step: float, nesterov: bool = False, lam_lap: float = 0.0,
-                 huber: tuple | None = None):
+                 huber: tuple | None = None, loss_delta: float | None = None):
         self.P, self.step, self.nesterov = projector, float(step), bool(nesterov)
         self.lam_lap, self.huber = float(lam_lap), huber
+        self.loss_delta = None if loss_delta is None else float(loss_delta)
 
     def objective_grad(self, c, data, w=None, mu=0.0, work=None):
         """(value float64[1], grad) of the whole objective at c."""
-        loss, grad, _ = self.P.loss_grad(c, data, w, mu, want_resid=False)
+        if self.loss_delta is None:
+            loss, grad, _ = self.P.loss_grad(c, data, w, mu, want_resid=False)
+        else:
+            # Huber loss of the residual (+ mu |c|^2): y = w h'(Ac - I), grad = A^T y + 2 mu c
+            _f32(data, self.P.data_shape, "data", self.P.device)
+            if w is not None:
+                _f32(w, self.P.data_shape, "w", self.P.device)
+            I = self.P.forward(c)
+            loss = torch.zeros(1, dtype=torch.float64, device=c.device)
+            y = torch.empty_like(I)
+            call("tt_huber_loss", C.c_void_p(I.data_ptr()), C.c_void_p(data.data_ptr()),
+                 C.c_void_p(w.data_ptr()) if w is not None else None, I.numel(), self.loss_delta,
+                 C.c_void_p(y.data_ptr()), C.c_void_p(loss.data_ptr()), _stream(c))
+            if mu:
+                call("tt_sumsq", C.c_void_p(c.data_ptr()), c.numel(), float(mu), C.c_void_p(loss.data_ptr()),
+                     _stream(c))
+            grad = self.P.adjoint(y, beta=2.0 * mu, c=c)
         if self.lam_lap:
             laplacian_reg(c, self.lam_lap, grad, loss, work)
         if self.huber is not None:

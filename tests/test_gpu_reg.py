@@ -72,3 +72,31 @@ def test_gradient_descent_nesterov_parity():
     assert np.all(np.abs(losses - losses_ref) <= 1e-5 * np.abs(losses_ref))
     assert rel_l2(c.cpu().numpy(), c_ref) <= 1e-5
     assert losses[-1] < losses[0]
+
+
+def test_gradient_descent_huber_loss_parity():
+    """Robust data term: fixed-step descent on sum h(Ac - I) + mu |c|^2 with outliers in the data."""
+    w = synth.WORKLOADS["c1"]
+    og = oracle.Geometry.from_workload(w)
+    c_true = phantom.coefficients(w).astype(np.float64)
+    data = oracle.project(og, c_true)
+    rng = np.random.default_rng(24)
+    out = rng.random(data.shape) < 0.01
+    data[out] += 50.0 * rng.standard_normal(int(out.sum()))
+    data = data.astype(np.float32).astype(np.float64)
+    v = rng.standard_normal(og.vol_shape)
+    for _ in range(8):
+        v = oracle.adjoint(og, oracle.project(og, v))
+        nrm = np.linalg.norm(v)
+        v /= nrm
+    delta, mu = 0.5, 1e-3
+    step = 1.0 / (1.05 * nrm / delta + 2 * mu)
+    c_ref, losses_ref = gradient_descent(og, np.zeros(og.vol_shape), data, step, 8, mu=mu, loss_delta=delta)
+    P = gpu_projector(og)
+    c = torch.zeros(P.vol_shape, device=DEV)
+    gd = GradientDescent(P, step, loss_delta=delta)
+    losses = gd.run(c, torch.from_numpy(data.astype(np.float32)).to(DEV), None, mu, 8).cpu().numpy()
+    print("huber-loss gd", losses[0], losses[-1], "ref", losses_ref[-1])
+    assert np.all(np.abs(losses - losses_ref) <= 1e-5 * np.abs(losses_ref))
+    assert rel_l2(c.cpu().numpy(), c_ref) <= 1e-5
+    assert losses[-1] < losses[0]

@@ -122,3 +122,16 @@ def test_regulariser_argument_errors_without_device():
     assert lib.tt_gd_step(p, p, None, 4, 0.1, 0.0, None) == -1
     assert lib.tt_gd_step(p, p, p, 4, float("inf"), 0.0, None) == -1
     assert lib.tt_gd_step(None, None, None, 0, 0.1, 0.0, None) == 0
+
+
+def test_huber_loss_argument_errors_without_device():
+    lib = _lib().lib()
+    buf = (C.c_float * 64)()
+    p = C.cast(buf, C.c_void_p)
+    d = (C.c_double * 1)()
+    dp = C.cast(d, C.c_void_p)
+    assert lib.tt_huber_loss(p, p, None, 4, 0.0, p, dp, None) == -1
+    assert lib.tt_huber_loss(None, p, None, 4, 0.5, p, dp, None) == -1
+    assert lib.tt_huber_loss(None, None, None, 0, 0.5, None, None, None) == 0
+    assert lib.tt_sumsq(p, 4, 1.0, None, None) == -1
+    assert lib.tt_sumsq(p, -2, 1.0, dp, None) == -2

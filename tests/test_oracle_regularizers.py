@@ -15,7 +15,7 @@ import numpy as np
 
 import oracle
 from oracle.dense import dense_A
-from oracle.regularizers import gradient_descent, huber_reg, laplacian, laplacian_reg, nesterov_momentum
+from oracle.regularizers import gradient_descent, huber_loss, huber_reg, laplacian, laplacian_reg, nesterov_momentum
 from geoms import tiny
 
 
@@ -103,3 +103,27 @@ def test_gradient_descent_first_step_and_convergence():
     c_long, _ = gradient_descent(g, c0, data, step, 1500, mu=mu, lam_lap=lam)
     assert np.linalg.norm(c_long - c_star) / np.linalg.norm(c_star) < 1e-12
     assert nesterov_momentum(1) == 0.0 and abs(nesterov_momentum(4) - 0.5) < 1e-15
+
+
+def test_huber_loss_small_residuals_and_fd():
+    g, data = _small_problem()
+    rng = np.random.default_rng(6)
+    c = rng.standard_normal(g.vol_shape)
+    # a width above every residual: the Huber loss is the squared loss / (2 delta)
+    r = oracle.project(g, c) - data
+    delta = 1.01 * np.abs(r).max()
+    v, grad = huber_loss(g, c, data, delta)
+    l2, g2, _ = oracle.loss_grad(g, c, data, None, 0.0)
+    assert abs(v - l2 / (2 * delta)) < 1e-12 * l2 and np.abs(grad - g2 / (2 * delta)).max() < 1e-12 * np.abs(g2).max()
+    # a narrow width: central differences (piecewise quadratic; steps small against the kink distances)
+    delta = 0.2 * np.abs(r).max()
+    w = rng.uniform(0.5, 1.5, g.data_shape)
+    v, grad = huber_loss(g, c, data, delta, w)
+    h = 1e-7
+    for _ in range(8):
+        idx = tuple(int(rng.integers(0, m)) for m in c.shape)
+        cp, cm = c.copy(), c.copy()
+        cp[idx] += h
+        cm[idx] -= h
+        fd = (huber_loss(g, cp, data, delta, w)[0] - huber_loss(g, cm, data, delta, w)[0]) / (2 * h)
+        assert abs(fd - grad[idx]) < 1e-5 * max(1.0, abs(grad[idx]))
