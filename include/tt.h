@@ -62,7 +62,7 @@ enum { TT_MAP_FP32 = 0, TT_MAP_BF16 = 1 };
  * during tt_create only. */
 typedef struct tt_geometry {
     int32_t nx, ny, nz;         /* volume shape, unit voxels (a = b = 1) */
-    int32_t ell_max;            /* even, 0..16 */
+    int32_t ell_max;            /* even, 0..16 (tt_create: 0..12) */
     int32_t n_proj;             /* number of goniometer settings s */
     int32_t nj, nk;             /* raster (detector pixel) grid */
     int32_t n_seg;              /* azimuthal detector segments, 1..64 */
@@ -86,7 +86,7 @@ typedef struct tt_ctx tt_ctx;
  * R_s = R_beta(beta_s) R_alpha(alpha_s), the ray frames and B_{sc,i} in
  * float64 on the host, uploads device tables and allocates work buffers.
  * Synchronous.  On failure *out is NULL. */
-int tt_create(const tt_geometry *geom, tt_ctx **out);
+int tt_create(const tt_geometry *geom, tt_ctx **out);  /* TT_EUNSUPPORTED for ell_max > 12 */
 /* Waits for the context's stream, then frees its tables and buffers. */
 void tt_destroy(tt_ctx *ctx);
 

@@ -231,6 +231,10 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.C = num_coeffs(g.ell_max);
     d.Cp = round_up(d.C, 16);
+    if (d.Cp > 96) {  // the adjoint keeps Cp/16 <= 6 accumulator tiles per wave
+        delete c;
+        return fail(TT_EUNSUPPORTED, "projector supports ell_max <= 12 (at most 96 padded coefficients)");
+    }
     d.S = g.n_proj; d.nj = g.nj; d.nk = g.nk; d.nseg = g.n_seg;
     d.step = (float)g.step;
     d.joseph = 0;

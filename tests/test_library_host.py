@@ -135,3 +135,13 @@ def test_huber_loss_argument_errors_without_device():
     assert lib.tt_huber_loss(None, None, None, 0, 0.5, None, None, None) == 0
     assert lib.tt_sumsq(p, 4, 1.0, None, None) == -1
     assert lib.tt_sumsq(p, -2, 1.0, dp, None) == -2
+
+
+def test_create_rejects_orders_above_twelve_without_device():
+    L = _lib()
+    lib = L.lib()
+    og = tiny(ell_max=14)
+    g = geometry_struct(og)
+    h = C.c_void_p()
+    assert lib.tt_create(C.byref(g), C.byref(h)) == -6
+    assert h.value is None
