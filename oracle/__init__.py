@@ -59,6 +59,7 @@ class Geom(C.Structure):
         ("p", C.c_double * 3), ("j", C.c_double * 3), ("k", C.c_double * 3),
         ("q0", C.c_double * 3), ("q90", C.c_double * 3),
         ("alpha", C.c_double * 3), ("beta", C.c_double * 3),
+        ("basis", C.c_int32), ("n_dirs", C.c_int32), ("dirs", _dp), ("width", C.c_double),
     ]
 
 
@@ -105,7 +106,8 @@ class Geometry:
     """Acquisition geometry; keeps the angle arrays alive for the C struct."""
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame, n_sub=3, step=1.0,
-                 seg_span=2 * np.pi, joff=None, koff=None, model="trilinear"):
+                 seg_span=2 * np.pi, joff=None, koff=None, model="trilinear", basis="sh", dirs=None,
+                 width=None):
         self.n = tuple(int(v) for v in n)
         self.ell_max = int(ell_max)
         self.inner = _f64(inner)
@@ -118,8 +120,18 @@ class Geometry:
         if model not in ("trilinear", "joseph"):
             raise ValueError("model must be 'trilinear' or 'joseph'")
         self.model = model
+        if basis not in ("sh", "gk", "nn"):
+            raise ValueError("basis must be 'sh', 'gk' or 'nn'")
+        self.basis = basis
+        self.dirs = None if basis == "sh" else _f64(dirs).reshape(-1, 3)
+        self.width = None if basis != "gk" else float(width)
         g = Geom()
         g.model = 1 if model == "joseph" else 0
+        g.basis = {"sh": 0, "gk": 1, "nn": 2}[basis]
+        if basis != "sh":
+            g.n_dirs = self.dirs.shape[0]
+            g.dirs = _p(self.dirs)
+            g.width = self.width if basis == "gk" else 0.0
         g.nx, g.ny, g.nz = self.n
         g.ell_max = self.ell_max
         g.n_proj = len(self.inner)
@@ -148,7 +160,7 @@ class Geometry:
 
     @property
     def n_coeff(self):
-        return num_coeffs(self.ell_max)
+        return num_coeffs(self.ell_max) if self.basis == "sh" else self.dirs.shape[0]
 
     @property
     def vol_shape(self):

@@ -63,6 +63,10 @@ typedef struct {
     const double *joff;   /* delta j_s (may be NULL) */
     const double *koff;   /* delta k_s (may be NULL) */
     double p[3], j[3], k[3], q0[3], q90[3], alpha[3], beta[3];
+    int32_t basis;        /* 0: spherical harmonics; 1: Gaussian kernels; 2: nearest neighbour */
+    int32_t n_dirs;       /* grid directions of the kernel bases */
+    const double *dirs;   /* [n_dirs][3] */
+    double width;         /* Gaussian kernel width (radians) */
 } og_geom;
 
 /* ------------------------------------------------------------------------ */
@@ -168,9 +172,41 @@ static void og_rt(const double *R, const double *v, double *out)
 /* over segment c, by an n_sub-node midpoint rule.  B[s][c][i].             */
 /* ------------------------------------------------------------------------ */
 
+/* Number of basis functions: SH count for ell_max, else the grid size. */
+int og_n_basis(const og_geom *g) { return g->basis == 0 ? og_num_coeffs(g->ell_max) : g->n_dirs; }
+
+/* Kernel bases on a grid of directions n_i (sect. 3.3 "Basis sets"); both
+ * are antipodally symmetric like the scattering they describe:
+ *   Gaussian kernels   f_i(q) = exp(-w_i^2 / (2 width^2)),
+ *                      w_i = angle between q and the nearer of +-n_i;
+ *   nearest neighbour  f_i(q) = 1 if n_i is the grid direction nearest to
+ *                      +-q (ties to the lowest index), else 0. */
+static void og_kernel_basis(const og_geom *g, const double *q, double *out)
+{
+    int best = 0;
+    double best_c = -1.0;
+    for (int i = 0; i < g->n_dirs; ++i) {
+        const double *n = g->dirs + 3 * i;
+        double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        double c = fabs(n[0] * q[0] + n[1] * q[1] + n[2] * q[2]) / nn;
+        if (c > 1.0) c = 1.0;
+        if (g->basis == 1) {
+            double w = acos(c);
+            out[i] = exp(-w * w / (2.0 * g->width * g->width));
+        } else {
+            out[i] = 0.0;
+            if (c > best_c) {
+                best_c = c;
+                best = i;
+            }
+        }
+    }
+    if (g->basis == 2) out[best] = 1.0;
+}
+
 void og_basis_matrix(const og_geom *g, double *B)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
     double *y = (double *)malloc(sizeof(double) * C);
     for (int s = 0; s < g->n_proj; ++s) {
         double R[9];
@@ -183,7 +219,10 @@ void og_basis_matrix(const og_geom *g, double *B)
                 double q[3], qs[3];
                 for (int a = 0; a < 3; ++a) q[a] = cos(phi) * g->q0[a] + sin(phi) * g->q90[a];
                 og_rt(R, q, qs);
-                og_sh(g->ell_max, qs, y);
+                if (g->basis == 0)
+                    og_sh(g->ell_max, qs, y);
+                else
+                    og_kernel_basis(g, qs, y);
                 for (int i = 0; i < C; ++i) row[i] += y[i] / g->n_sub;
             }
         }
@@ -384,7 +423,7 @@ static double og_joseph_weight(const og_geom *g, const og_frame *f, int j, int k
 /* Forward model (Eq. forward_model): I[s][j][k][c] = sum_i B[s][c][i] J_i. */
 void og_project(const og_geom *g, const double *B, const double *c, double *I)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
     int64_t rows = (int64_t)g->n_proj * g->nj;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t sj = 0; sj < rows; ++sj) {
@@ -413,7 +452,7 @@ void og_project(const og_geom *g, const double *B, const double *c, double *I)
 void og_project_rays(const og_geom *g, const double *B, const double *c, int64_t n_rays,
                      const int32_t *sjk, double *out)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < n_rays; ++r) {
         int s = sjk[3 * r], j = sjk[3 * r + 1], k = sjk[3 * r + 2];
@@ -467,7 +506,7 @@ static void og_ray_splat(const og_geom *g, const og_frame *f, int j, int k, cons
  * thread count is capped so the private volumes fit in mem_budget bytes. */
 void og_adjoint(const og_geom *g, const double *B, const double *y, double *out, double mem_budget)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
     int64_t nv = (int64_t)g->nx * g->ny * g->nz * C;
     int nt = 1;
 #ifdef _OPENMP
@@ -523,7 +562,7 @@ void og_adjoint(const og_geom *g, const double *B, const double *y, double *out,
 void og_adjoint_voxels(const og_geom *g, const double *B, const double *y, int64_t n_vox,
                        const int32_t *xyz, double *out)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t v = 0; v < n_vox; ++v) {
         int ix = xyz[3 * v], iy = xyz[3 * v + 1], iz = xyz[3 * v + 2];
@@ -609,7 +648,7 @@ void og_splat_projection(const og_geom *g, int s, const double *yf, int nu, doub
 double og_loss_grad(const og_geom *g, const double *B, const double *c, const double *data,
                     const double *w, double mu, double *grad, double *resid, double mem_budget)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
     int64_t nd = (int64_t)g->n_proj * g->nj * g->nk * g->n_seg;
     int64_t nc = (int64_t)g->nx * g->ny * g->nz * C;
     double *r = resid ? resid : (double *)malloc(sizeof(double) * nd);
@@ -654,7 +693,7 @@ int og_lbfgs(const og_geom *g, const double *B, double *c, const double *data, c
              double mu, int m, int max_iter, double tol, double *hist, double *final_rel,
              double mem_budget)
 {
-    int C = og_num_coeffs(g->ell_max);
+    int C = og_n_basis(g);
     int64_t nd = (int64_t)g->n_proj * g->nj * g->nk * g->n_seg;
     int64_t n = (int64_t)g->nx * g->ny * g->nz * C;
     double *r = (double *)malloc(sizeof(double) * nd);

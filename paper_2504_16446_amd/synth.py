@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "WORKLOADS", "lab_frame", "angles", "gaussian", "uniform",
-    "twisted_fibre_field", "multi_bundle_field", "noise",
+    "twisted_fibre_field", "multi_bundle_field", "noise", "truncated_icosahedron_dirs", "hemisphere_dirs",
 ]
 
 
@@ -205,3 +205,44 @@ def zh_lobe_weights(degree):
     """
     d = np.asarray(degree, dtype=np.float64)
     return np.stack([np.ones_like(d), 20.0 * d / 7.0, 8.0 * d / 7.0], axis=-1)
+
+
+def truncated_icosahedron_dirs():
+    """Face-centre directions of the truncated icosahedron, one of each antipodal
+    pair (16 directions): its 12 pentagons sit over the vertices of the regular
+    icosahedron with vertices (0, +-1, +-g) and cyclic permutations (g the
+    golden ratio), its 20 hexagons over that icosahedron's face centres.  A
+    grid for the nearest-neighbour basis."""
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    ico = []
+    for s1 in (1.0, -1.0):
+        for s2 in (1.0, -1.0):
+            base = (0.0, s1, s2 * g)
+            for k in range(3):
+                ico.append(base[k:] + base[:k])
+    ico = np.array(ico)
+    faces = []
+    n = len(ico)
+    for a in range(n):
+        for b in range(a + 1, n):
+            for c in range(b + 1, n):
+                if all(abs(np.linalg.norm(ico[p] - ico[q]) - 2.0) < 1e-9 for p, q in ((a, b), (a, c), (b, c))):
+                    faces.append(ico[[a, b, c]].mean(axis=0))
+    v = np.concatenate([ico, np.array(faces)])
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    keep = []
+    for p in v:  # one of each antipodal pair: first nonzero coordinate positive
+        if p[np.flatnonzero(np.abs(p) > 1e-12)[0]] > 0:
+            keep.append(p)
+    return np.array(keep)
+
+
+def hemisphere_dirs(n: int):
+    """n directions spread over the upper hemisphere (golden-angle spiral in
+    z = cos(theta) from 1 towards 0); a grid for the Gaussian-kernel basis."""
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (k + 0.5) / n
+    r = np.sqrt(1.0 - z * z)
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
