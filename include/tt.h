@@ -78,7 +78,25 @@ typedef struct tt_geometry {
     double q0[3], q90[3];       /* detector azimuth origin and +90 deg */
     double alpha_axis[3];       /* inner (rotation) stage axis */
     double beta_axis[3];        /* outer (tilt) stage axis */
+    /* Basis set of the per-voxel functions (sect. 3.3 "Basis sets"); zero
+     * (TT_BASIS_SH) selects the real spherical harmonics up to ell_max.  The
+     * kernel bases put one function on each of n_dirs grid directions
+     * dirs[n_dirs][3] (host, normalised internally), C = n_dirs <= 96:
+     *   TT_BASIS_GK: Gaussian kernels exp(-w^2 / (2 kernel_width^2)), w the
+     *                angle between q and the nearer of +-dir (radians);
+     *   TT_BASIS_NN: nearest neighbour, 1 on the directions q closer to +-dir
+     *                than to any other grid direction (ties to the lower
+     *                index), 0 elsewhere.
+     * Both are antipodally symmetric.  ell_max is ignored for them. */
+    int32_t basis;
+    int32_t n_dirs;
+    const double *dirs;
+    double kernel_width;
 } tt_geometry;
+
+#define TT_BASIS_SH 0
+#define TT_BASIS_GK 1
+#define TT_BASIS_NN 2
 
 typedef struct tt_ctx tt_ctx;
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libtt_hip.so")
 
 TT_MAP_FP32, TT_MAP_BF16 = 0, 1
 TT_PROJ_TRILINEAR, TT_PROJ_JOSEPH = 0, 1
+TT_BASIS_SH, TT_BASIS_GK, TT_BASIS_NN = 0, 1, 2
 KERNEL_CLASSES = ["map", "march", "fold", "backproject", "residual", "vector", "plan"]
 _ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EUNSUPPORTED"}
 
@@ -38,6 +39,8 @@ class Geometry(C.Structure):
         ("p", C.c_double * 3), ("j", C.c_double * 3), ("k", C.c_double * 3),
         ("q0", C.c_double * 3), ("q90", C.c_double * 3),
         ("alpha_axis", C.c_double * 3), ("beta_axis", C.c_double * 3),
+        ("basis", C.c_int32), ("n_dirs", C.c_int32), ("dirs", C.POINTER(C.c_double)),
+        ("kernel_width", C.c_double),
     ]
 
 

@@ -195,6 +195,24 @@ static int read_geometry(const tt_geometry *geom, Geometry &g)
     std::memcpy(g.q0, G.q0, sizeof g.q0); std::memcpy(g.q90, G.q90, sizeof g.q90);
     std::memcpy(g.alpha_axis, G.alpha_axis, sizeof g.alpha_axis);
     std::memcpy(g.beta_axis, G.beta_axis, sizeof g.beta_axis);
+    g.basis = G.basis;
+    g.dirs.clear();
+    g.kernel_width = 0.0;
+    if (G.basis != TT_BASIS_SH) {
+        if (G.basis != TT_BASIS_GK && G.basis != TT_BASIS_NN) return fail(TT_EINVAL, "unknown basis");
+        if (G.n_dirs < 1 || !G.dirs) return fail(TT_EINVAL, "kernel bases need n_dirs >= 1 grid directions");
+        if (G.n_dirs > 96) return fail(TT_EUNSUPPORTED, "at most 96 grid directions");
+        if (G.basis == TT_BASIS_GK && (!(G.kernel_width > 0.0) || !std::isfinite(G.kernel_width)))
+            return fail(TT_EINVAL, "kernel_width must be > 0");
+        g.kernel_width = G.kernel_width;
+        g.dirs.resize(3 * (size_t)G.n_dirs);
+        for (int i = 0; i < G.n_dirs; ++i) {
+            const double *d = G.dirs + 3 * i;
+            const double n = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!finite3(d) || !(n > 0.0)) return fail(TT_EINVAL, "grid directions must be finite and nonzero");
+            for (int a = 0; a < 3; ++a) g.dirs[3 * i + a] = d[a] / n;
+        }
+    }
     return TT_OK;
 }
 
@@ -229,18 +247,22 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
 
     Dims &d = c->d;
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
-    d.C = num_coeffs(g.ell_max);
+    d.C = basis_count(g);
     d.Cp = round_up(d.C, 16);
     if (d.Cp > 96) {  // the adjoint keeps Cp/16 <= 6 accumulator tiles per wave
         delete c;
-        return fail(TT_EUNSUPPORTED, "projector supports ell_max <= 12 (at most 96 padded coefficients)");
+        return fail(TT_EUNSUPPORTED, "projector supports ell_max <= 12 / 96 basis functions (96 padded coefficients)");
     }
     d.S = g.n_proj; d.nj = g.nj; d.nk = g.nk; d.nseg = g.n_seg;
     d.step = (float)g.step;
     d.joseph = 0;
-    // Even orders: Y(-q) = Y(q), and with segments over the full circle segment
-    // c + n_seg/2 probes exactly the antipodes of segment c.
-    const bool antipodal = std::fabs(g.seg_span - 2.0 * M_PI) < 1e-12 && g.n_seg % 2 == 0;
+    // Even orders: Y(-q) = Y(q) (and the Gaussian kernels are symmetric too), and
+    // with segments over the full circle segment c + n_seg/2 probes exactly the
+    // antipodes of segment c.
+    // (The nearest-neighbour basis is excluded: a node nearly equidistant from
+    // two grid directions may pick different ones for q and for the computed
+    // -q, so its antipodal segments agree only up to such ties.)
+    const bool antipodal = std::fabs(g.seg_span - 2.0 * M_PI) < 1e-12 && g.n_seg % 2 == 0 && g.basis != TT_BASIS_NN;
     d.U = antipodal ? g.n_seg / 2 : g.n_seg;
     if (d.U > 16) {
         delete c;

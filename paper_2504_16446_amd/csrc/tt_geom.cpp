@@ -30,6 +30,32 @@ namespace tt {
 
 int num_coeffs(int ell_max) { return (ell_max / 2 + 1) * (ell_max + 1); }
 
+int basis_count(const Geometry &g) { return g.basis == TT_BASIS_SH ? num_coeffs(g.ell_max) : (int)(g.dirs.size() / 3); }
+
+// Kernel basis functions at unit direction q (Gaussian kernels or nearest
+// neighbour on the grid g.dirs), antipodally symmetric.
+static void kernel_eval(const Geometry &g, const double *q, double *out)
+{
+    const int n = (int)(g.dirs.size() / 3);
+    int nearest = 0;
+    double best = -1.0;
+    for (int i = 0; i < n; ++i) {
+        const double *d = &g.dirs[3 * i];
+        const double c = std::min(1.0, std::fabs(d[0] * q[0] + d[1] * q[1] + d[2] * q[2]));
+        if (g.basis == TT_BASIS_GK) {
+            const double w = std::acos(c);
+            out[i] = std::exp(-0.5 * w * w / (g.kernel_width * g.kernel_width));
+        } else {
+            out[i] = 0.0;
+            if (c > best) {
+                best = c;
+                nearest = i;
+            }
+        }
+    }
+    if (g.basis == TT_BASIS_NN) out[nearest] = 1.0;
+}
+
 void sh_eval_one(int ell_max, const double *dir, double *out)
 {
     const double kFourPi = 4.0 * M_PI;
@@ -156,7 +182,7 @@ void cube_shadow(const double *ej, const double *ek, float *hull)
 
 void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector<double> &B)
 {
-    const int S = g.n_proj, C = num_coeffs(g.ell_max);
+    const int S = g.n_proj, C = basis_count(g);
     frames.resize(S);
     B.assign((size_t)S * g.n_seg * C, 0.0);
     std::vector<double> y(C);
@@ -203,7 +229,10 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
                 double qd[3], qs[3];
                 for (int a = 0; a < 3; ++a) qd[a] = std::cos(phi) * g.q0[a] + std::sin(phi) * g.q90[a];
                 rotate_inverse(q, qd, qs);
-                sh_eval_one(g.ell_max, qs, y.data());
+                if (g.basis == TT_BASIS_SH)
+                    sh_eval_one(g.ell_max, qs, y.data());
+                else
+                    kernel_eval(g, qs, y.data());
                 for (int i = 0; i < C; ++i) row[i] += y[i];
             }
             for (int i = 0; i < C; ++i) row[i] /= g.n_sub;

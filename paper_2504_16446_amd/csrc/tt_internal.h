@@ -17,7 +17,13 @@ struct Geometry {
     double step, seg_span;
     std::vector<double> inner, outer, joff, koff;
     double p[3], j[3], k[3], q0[3], q90[3], alpha_axis[3], beta_axis[3];
+    int basis = TT_BASIS_SH;
+    std::vector<double> dirs;  // [n][3], unit length (kernel bases)
+    double kernel_width = 0.0;
 };
+
+// Number of basis functions of a geometry (SH count or grid size).
+int basis_count(const Geometry &g);
 
 // Ray frame of one projection, float64, in centred sample coordinates.
 // The ray through pixel (j, k) is o + j e_j + k e_k + t d.

@@ -55,7 +55,7 @@ class Projector:
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame=None, n_sub=3, step=1.0,
                  seg_span=2 * math.pi, joff=None, koff=None, map_precision="fp32", device=None,
-                 model="trilinear"):
+                 model="trilinear", basis="sh", dirs=None, width=None):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("Projector runs on a HIP device only")
@@ -77,6 +77,16 @@ class Projector:
         for field, key in (("p", "p"), ("j", "j"), ("k", "k"), ("q0", "q0"), ("q90", "q90"),
                            ("alpha_axis", "alpha"), ("beta_axis", "beta")):
             getattr(g, field)[:] = [float(x) for x in frame[key]]
+        if basis not in ("sh", "gk", "nn"):
+            raise ValueError("basis must be 'sh', 'gk' or 'nn'")
+        if basis != "sh":
+            grid = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+            self._keep.append(grid)
+            g.basis = _lib.TT_BASIS_GK if basis == "gk" else _lib.TT_BASIS_NN
+            g.n_dirs = grid.shape[0]
+            g.dirs = _dptr(grid)
+            g.kernel_width = float(width) if basis == "gk" else 0.0
+        self.basis = basis
         self.geometry = g
         handle = C.c_void_p()
         with torch.cuda.device(self.device):

@@ -15,6 +15,12 @@ def rel_max(got, ref):
 def gpu_projector(og, **kw):
     """Projector with exactly the oracle geometry's parameters."""
     from paper_2504_16446_amd.projector import Projector
+    if getattr(og, "basis", "sh") != "sh":
+        kw.setdefault("basis", og.basis)
+        kw.setdefault("dirs", og.dirs)
+        kw.setdefault("width", og.width)
+    if getattr(og, "model", "trilinear") != "trilinear":
+        kw.setdefault("model", og.model)
     return Projector(og.n, og.ell_max, og.inner, og.outer, og.nj, og.nk, og.n_seg,
                      frame=og.frame, n_sub=og.n_sub, step=og.step, seg_span=og.seg_span,
                      joff=og.joff, koff=og.koff, **kw)
@@ -38,4 +44,9 @@ def geometry_struct(og, precision=0):
     for field, key in (("p", "p"), ("j", "j"), ("k", "k"), ("q0", "q0"), ("q90", "q90"),
                        ("alpha_axis", "alpha"), ("beta_axis", "beta")):
         getattr(g, field)[:] = og.frame[key]
+    if getattr(og, "basis", "sh") != "sh":
+        g.basis = {"gk": 1, "nn": 2}[og.basis]
+        g.n_dirs = og.dirs.shape[0]
+        g.dirs = og.dirs.ctypes.data_as(P)
+        g.kernel_width = og.width or 0.0
     return g

@@ -145,3 +145,44 @@ def test_create_rejects_orders_above_twelve_without_device():
     h = C.c_void_p()
     assert lib.tt_create(C.byref(g), C.byref(h)) == -6
     assert h.value is None
+
+
+@pytest.mark.parametrize("basis,width", [("gk", 0.35), ("nn", None)])
+def test_kernel_basis_matrix_matches_oracle(basis, width):
+    from paper_2504_16446_amd import synth as _s
+    dirs = _s.hemisphere_dirs(20) if basis == "gk" else _s.truncated_icosahedron_dirs()
+    og = oracle.Geometry((6, 7, 5), 0, *geoms_tilted(), 9, 8, 8, _s.lab_frame(), basis=basis, dirs=dirs,
+                         width=width)
+    g = geometry_struct(og)
+    B = np.empty((og.n_proj, og.n_seg, og.n_coeff))
+    _lib().call("tt_geometry_basis", C.byref(g), B.ctypes.data_as(C.POINTER(C.c_double)))
+    ref = og.B()
+    if basis == "nn":
+        # both sides pick the nearest grid direction; ties cannot occur at these nodes
+        assert np.array_equal(B, ref)
+    else:
+        assert np.abs(B - ref).max() < 1e-13
+
+
+def geoms_tilted():
+    from geoms import tilted_angles
+    return tilted_angles(4, (0.0, 25.0, 45.0), span_deg=360.0)
+
+
+def test_kernel_basis_argument_errors_without_device():
+    og = tiny()
+    g = geometry_struct(og)
+    B = np.empty(4096)
+    Bp = B.ctypes.data_as(C.POINTER(C.c_double))
+    lib = _lib().lib()
+    g.basis = 1
+    g.n_dirs = 0
+    assert lib.tt_geometry_basis(C.byref(g), Bp) == -1
+    d = np.array([[0.0, 0.0, 1.0]] * 3)
+    g.n_dirs, g.dirs = 3, d.ctypes.data_as(C.POINTER(C.c_double))
+    g.kernel_width = 0.0
+    assert lib.tt_geometry_basis(C.byref(g), Bp) == -1
+    g.kernel_width = 0.3
+    assert lib.tt_geometry_basis(C.byref(g), Bp) == 0
+    g.basis = 7
+    assert lib.tt_geometry_basis(C.byref(g), Bp) == -1
