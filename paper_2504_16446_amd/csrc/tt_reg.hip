@@ -8,41 +8,73 @@
 namespace tt {
 
 // One block per (x, y) row of the coefficient volume c[x][y][z][C]: the row's
-// z * C floats are contiguous, z neighbours are +-C inside the row, y and x
-// neighbours are the same offsets in the adjacent rows (zero outside).
+// z * C floats are contiguous; the block stages its own row in LDS (for the
+// +-C z neighbours) and reads the four adjacent rows (x +- 1, y +- 1, zero
+// outside) as float4 streams when rows are 16-byte aligned.
 //   ACC = false: out = Lap(in), value += lam sum Lap(in)^2 (if value)
 //   ACC = true:  out += scale * Lap(in)
+constexpr int kLapRowMax = 12288;  // floats of one staged row (48 KiB)
+
+typedef float f4r __attribute__((ext_vector_type(4)));
+
 template <bool ACC>
 __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ in, int nx, int ny, int nz, int C,
                                                    float *__restrict__ out, float scale, double lam,
-                                                   double *__restrict__ value)
+                                                   double *__restrict__ value, int aligned)
 {
     __shared__ double ws[4];
+    __shared__ float rowc[kLapRowMax];
     const int x = blockIdx.x / ny, y = blockIdx.x % ny;
-    const int row = nz * C;  // < 2^31 (checked by the caller)
+    const int row = nz * C;  // <= kLapRowMax (checked by the caller)
     const long long base = ((long long)x * ny + y) * row;
     const float *r0 = in + base;
-    const float *rxm = x > 0 ? r0 - (long long)ny * row : nullptr;
-    const float *rxp = x + 1 < nx ? r0 + (long long)ny * row : nullptr;
-    const float *rym = y > 0 ? r0 - row : nullptr;
-    const float *ryp = y + 1 < ny ? r0 + row : nullptr;
+    const long long sx = (long long)ny * row;
+    const float *nb[4] = {x > 0 ? r0 - sx : nullptr, x + 1 < nx ? r0 + sx : nullptr, y > 0 ? r0 - row : nullptr,
+                          y + 1 < ny ? r0 + row : nullptr};
+    const bool vec = aligned && (row & 3) == 0;  // every row starts 16-byte aligned
+    if (vec) {
+        for (int e4 = threadIdx.x; e4 < row / 4; e4 += 256)
+            reinterpret_cast<f4r *>(rowc)[e4] = reinterpret_cast<const f4r *>(r0)[e4];
+    } else {
+        for (int e = threadIdx.x; e < row; e += 256) rowc[e] = r0[e];
+    }
+    __syncthreads();
     double ss = 0.0;
-    const float invC = 1.0f / (float)C;  // exact quotient: e < 2^22 and C <= 2^8 here
-    for (int e = threadIdx.x; e < row; e += 256) {
-        const int z = C <= 256 && row < (1 << 22) ? (int)(((float)e + 0.5f) * invC) : e / C;
-        const float v = r0[e];
-        float acc = -6.0f * v;
-        if (z > 0) acc += r0[e - C];
-        if (z + 1 < nz) acc += r0[e + C];
-        if (rym) acc += rym[e];
-        if (ryp) acc += ryp[e];
-        if (rxm) acc += rxm[e];
-        if (rxp) acc += rxp[e];
-        if (ACC) {
-            out[base + e] = fmaf(scale, acc, out[base + e]);
-        } else {
-            out[base + e] = acc;
-            ss += (double)acc * (double)acc;
+    if (vec) {
+        for (int e4 = threadIdx.x; e4 < row / 4; e4 += 256) {
+            f4r acc = -6.0f * reinterpret_cast<const f4r *>(rowc)[e4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (nb[q]) acc += reinterpret_cast<const f4r *>(nb[q])[e4];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int e = 4 * e4 + l;
+                if (e >= C) acc[l] += rowc[e - C];
+                if (e + C < row) acc[l] += rowc[e + C];
+            }
+            f4r *o = reinterpret_cast<f4r *>(out + base) + e4;
+            if (ACC) {
+                *o = scale * acc + *o;
+            } else {
+                *o = acc;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) ss += (double)acc[l] * (double)acc[l];
+            }
+        }
+    } else {
+        for (int e = threadIdx.x; e < row; e += 256) {
+            float acc = -6.0f * rowc[e];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (nb[q]) acc += nb[q][e];
+            if (e >= C) acc += rowc[e - C];
+            if (e + C < row) acc += rowc[e + C];
+            if (ACC) {
+                out[base + e] = fmaf(scale, acc, out[base + e]);
+            } else {
+                out[base + e] = acc;
+                ss += (double)acc * (double)acc;
+            }
         }
     }
     if (!ACC && value) {
@@ -55,24 +87,46 @@ hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, d
                                 double *value, hipStream_t st)
 {
     const long long rows = (long long)nx * ny;
-    if (rows > 0x7fffffffLL || (long long)nz * C > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (rows > 0x7fffffffLL || (long long)nz * C > kLapRowMax) return hipErrorNotSupported;
+    const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(work) |
+                          reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
     hipLaunchKernelGGL(k_laplacian<false>, dim3((unsigned)rows), dim3(256), 0, st, c, nx, ny, nz, C, work, 0.0f, lam,
-                       value);
+                       value, aligned);
     hipLaunchKernelGGL(k_laplacian<true>, dim3((unsigned)rows), dim3(256), 0, st, work, nx, ny, nz, C, grad,
-                       (float)(2.0 * lam), 0.0, nullptr);
+                       (float)(2.0 * lam), 0.0, nullptr, aligned);
     return hipGetLastError();
 }
 
 // value += lam sum h(c), grad += lam h'(c); h(x) = x^2/(2 delta) for |x| <= delta, else |x| - delta/2.
+// Float4 streams over the first 4 * (n / 4) elements when both arrays are
+// 16-byte aligned, scalar for the rest.
+__device__ __forceinline__ double huber_h(float x, float delta)
+{
+    const float a = fabsf(x);
+    return a <= delta ? 0.5 * (double)x * (double)x / (double)delta : (double)a - 0.5 * (double)delta;
+}
+
 __global__ __launch_bounds__(256) void k_huber(const float *__restrict__ c, long long n, float delta, float lam,
-                                               float *__restrict__ grad, double *__restrict__ value)
+                                               float *__restrict__ grad, double *__restrict__ value, int aligned)
 {
     __shared__ double ws[4];
     const float inv = 1.0f / delta;
     double hs = 0.0;
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
-        const float x = c[e], a = fabsf(x);
-        hs += a <= delta ? 0.5 * (double)x * (double)x / (double)delta : (double)a - 0.5 * (double)delta;
+    const long long stride = (long long)gridDim.x * 256;
+    long long n4 = aligned ? n / 4 : 0;
+    for (long long e4 = blockIdx.x * 256LL + threadIdx.x; e4 < n4; e4 += stride) {
+        const f4r x = reinterpret_cast<const f4r *>(c)[e4];
+        f4r g = reinterpret_cast<const f4r *>(grad)[e4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            hs += huber_h(x[l], delta);
+            g[l] = fmaf(lam, fminf(1.0f, fmaxf(-1.0f, x[l] * inv)), g[l]);
+        }
+        reinterpret_cast<f4r *>(grad)[e4] = g;
+    }
+    for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
+        const float x = c[e];
+        hs += huber_h(x, delta);
         grad[e] = fmaf(lam, fminf(1.0f, fmaxf(-1.0f, x * inv)), grad[e]);
     }
     if (value) {
@@ -84,9 +138,10 @@ __global__ __launch_bounds__(256) void k_huber(const float *__restrict__ c, long
 hipError_t launch_huber_reg(const float *c, long long n, double delta, double lam, float *grad, double *value,
                             hipStream_t st)
 {
-    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
+    const int blocks = (int)std::min<long long>((n / 4 + 255) / 256, 4096);
     hipLaunchKernelGGL(k_huber, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, n, (float)delta, (float)lam, grad,
-                       value);
+                       value, aligned);
     return hipGetLastError();
 }
 
@@ -139,11 +194,21 @@ hipError_t launch_sumsq(const float *x, long long n, double scale, double *value
     return hipGetLastError();
 }
 
-// c_new = y - step g; y = c_new + m (c_new - c); c = c_new.
+// c_new = y - step g; y = c_new + m (c_new - c); c = c_new (float4 streams when aligned).
 __global__ __launch_bounds__(256) void k_nesterov(float *__restrict__ c, float *__restrict__ y,
-                                                  const float *__restrict__ g, long long n, float step, float m)
+                                                  const float *__restrict__ g, long long n, float step, float m,
+                                                  int aligned)
 {
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const long long stride = (long long)gridDim.x * 256;
+    const long long n4 = aligned ? n / 4 : 0;
+    for (long long e4 = blockIdx.x * 256LL + threadIdx.x; e4 < n4; e4 += stride) {
+        const f4r yv = reinterpret_cast<const f4r *>(y)[e4], gv = reinterpret_cast<const f4r *>(g)[e4];
+        const f4r cv = reinterpret_cast<const f4r *>(c)[e4];
+        const f4r cn = yv - step * gv;
+        reinterpret_cast<f4r *>(y)[e4] = cn + m * (cn - cv);
+        reinterpret_cast<f4r *>(c)[e4] = cn;
+    }
+    for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
         const float cn = fmaf(-step, g[e], y[e]);
         y[e] = fmaf(m, cn - c[e], cn);
         c[e] = cn;
@@ -152,8 +217,10 @@ __global__ __launch_bounds__(256) void k_nesterov(float *__restrict__ c, float *
 
 hipError_t launch_nesterov(float *c, float *y, const float *g, long long n, float step, float m, hipStream_t st)
 {
-    const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_nesterov, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, y, g, n, step, m);
+    const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(y) |
+                          reinterpret_cast<uintptr_t>(g)) & 15) == 0;
+    const int blocks = (int)std::min<long long>((n / 4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_nesterov, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, y, g, n, step, m, aligned);
     return hipGetLastError();
 }
 
