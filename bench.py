@@ -247,7 +247,7 @@ def regulariser_bench(dev, reps=5):
     cases = (("laplacian", 20.0, lambda: laplacian_reg(c, 1e-2, g, val, work)),
              ("huber", 12.0, lambda: huber_reg(c, 0.05, 1e-2, g, val)),
              ("gd_step", 20.0, lambda: call("tt_gd_step", C.c_void_p(c.data_ptr()), C.c_void_p(y.data_ptr()),
-                                            C.c_void_p(g.data_ptr()), n, 1e-6, 0.5,
+                                            C.c_void_p(g.data_ptr()), None, n, 1e-6, 0.5,
                                             C.c_void_p(stream.cuda_stream))))
     for name, per, fn in cases:
         fn()

@@ -298,10 +298,13 @@ int tt_huber_loss(const float *I, const float *data, const float *w, int64_t n, 
 /* value[0] += scale * sum x^2 over n floats (float64 accumulation). */
 int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *stream);
 /* One gradient step with momentum m on n floats, g = grad f(y):
- * c_new = y - step g, y = c_new + m (c_new - c), c = c_new.  m = 0 is plain
- * gradient descent (y then tracks c); Nesterov's schedule is m_k = (k-1)/(k+2).
- * c, y and g must be distinct buffers. */
-int tt_gd_step(float *c, float *y, const float *g, int64_t n, float step, float momentum, void *stream);
+ * c_new = y - step p g, y = c_new + m (c_new - c), c = c_new, with p an
+ * optional diagonal preconditioner (n positive floats, NULL = 1; the paper's
+ * loss functions "can be given a preconditioner to weight the gradient").
+ * m = 0 is plain gradient descent (y then tracks c); Nesterov's schedule is
+ * m_k = (k-1)/(k+2).  c, y, g and p must be distinct buffers. */
+int tt_gd_step(float *c, float *y, const float *g, const float *precond, int64_t n, float step, float momentum,
+               void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Derived per-voxel quantities (the paper's section on deriving standard    */

@@ -14,8 +14,9 @@ optimisers of sect. 3.5 ("Optimization"):
   with a continuous derivative clamp(x / delta, -1, 1)).
 * Huber loss (robust regression on the residual, the HuberLoss of sect.
   3.5): sum w h(Ac - I) with the same h; its gradient is A^T (w h'(r)).
-* Gradient descent with a fixed step, optionally with Nesterov momentum:
-  c_{k+1} = y_k - step grad f(y_k), y_{k+1} = c_{k+1} + m_k (c_{k+1} - c_k),
+* Gradient descent with a fixed step, optionally with Nesterov momentum and a
+  diagonal preconditioner p (the paper's loss functions accept one):
+  c_{k+1} = y_k - step p grad f(y_k), y_{k+1} = c_{k+1} + m_k (c_{k+1} - c_k),
   m_k = (k - 1) / (k + 2) for k = 1, 2, ... (Nesterov's schedule), m_k = 0
   without momentum; y_0 = c_0.
 """
@@ -65,11 +66,13 @@ def nesterov_momentum(k: int) -> float:
 
 
 def gradient_descent(g, c0, data, step, iters, w=None, mu=0.0, lam_lap=0.0, huber=None, nesterov=False,
-                     loss_delta=None):
+                     loss_delta=None, precond=None):
     """Fixed-step gradient descent on the data term + mu |c|^2 + Laplacian + Huber terms.
 
     The data term is sum w (Ac - I)^2, or the Huber loss sum w h(Ac - I) of
     width loss_delta when that is given.  huber = (delta, lambda) or None.
+    precond: optional positive diagonal (array of c's shape) multiplying the
+    gradient in each step.
     Returns (c, losses) with losses[k] the objective at the point whose
     gradient step k takes (y_k)."""
     c = np.asarray(c0, dtype=np.float64).copy()
@@ -88,7 +91,7 @@ def gradient_descent(g, c0, data, step, iters, w=None, mu=0.0, lam_lap=0.0, hube
             fh, gh = huber_reg(y, huber[0], huber[1])
             f, grad = f + fh, grad + gh
         losses.append(f)
-        c_new = y - step * grad
+        c_new = y - step * (grad if precond is None else precond * grad)
         m = nesterov_momentum(k) if nesterov else 0.0
         y = c_new + m * (c_new - c)
         c = c_new

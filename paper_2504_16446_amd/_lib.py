@@ -88,7 +88,7 @@ _SIGS = [
     ("tt_tensor_properties", C.c_int, [_fp, C.c_int64, C.c_int, _fp, _vp]),
     ("tt_laplacian_reg", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _fp, _fp, _dp, _vp]),
     ("tt_huber_reg", C.c_int, [_fp, C.c_int64, C.c_double, C.c_double, _fp, _dp, _vp]),
-    ("tt_gd_step", C.c_int, [_fp, _fp, _fp, C.c_int64, C.c_float, C.c_float, _vp]),
+    ("tt_gd_step", C.c_int, [_fp, _fp, _fp, _fp, C.c_int64, C.c_float, C.c_float, _vp]),
     ("tt_huber_loss", C.c_int, [_fp, _fp, _fp, C.c_int64, C.c_double, _fp, _dp, _vp]),
     ("tt_sumsq", C.c_int, [_fp, C.c_int64, C.c_double, _dp, _vp]),
     ("tt_last_error", C.c_char_p, []),

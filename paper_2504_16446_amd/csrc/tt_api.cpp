@@ -871,13 +871,14 @@ int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *strea
     return TT_OK;
 }
 
-int tt_gd_step(float *c, float *y, const float *g, int64_t n, float step, float momentum, void *stream)
+int tt_gd_step(float *c, float *y, const float *g, const float *precond, int64_t n, float step, float momentum,
+               void *stream)
 {
     if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
     if (!std::isfinite(step) || !std::isfinite(momentum)) return fail(TT_EINVAL, "bad step or momentum");
     if (n == 0) return TT_OK;
     if (!c || !y || !g) return fail(TT_EINVAL, "null pointer");
-    TT_HIP(launch_nesterov(c, y, g, n, step, momentum, (hipStream_t)stream));
+    TT_HIP(launch_nesterov(c, y, g, precond, n, step, momentum, (hipStream_t)stream));
     return TT_OK;
 }
 

@@ -115,7 +115,8 @@ hipError_t launch_huber_reg(const float *c, long long n, double delta, double la
 hipError_t launch_huber_loss(const float *I, const float *data, const float *w, long long n, double delta, float *y,
                              double *value, hipStream_t st);
 hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, hipStream_t st);
-hipError_t launch_nesterov(float *c, float *y, const float *g, long long n, float step, float m, hipStream_t st);
+hipError_t launch_nesterov(float *c, float *y, const float *g, const float *p, long long n, float step, float m,
+                           hipStream_t st);
 
 // Reductions: out[slot] = scale * sum of partials[0..n).
 hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,

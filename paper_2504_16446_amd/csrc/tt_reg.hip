@@ -194,33 +194,38 @@ hipError_t launch_sumsq(const float *x, long long n, double scale, double *value
     return hipGetLastError();
 }
 
-// c_new = y - step g; y = c_new + m (c_new - c); c = c_new (float4 streams when aligned).
+// c_new = y - step p g; y = c_new + m (c_new - c); c = c_new, with p a
+// diagonal preconditioner (1 when null); float4 streams when aligned.
 __global__ __launch_bounds__(256) void k_nesterov(float *__restrict__ c, float *__restrict__ y,
-                                                  const float *__restrict__ g, long long n, float step, float m,
-                                                  int aligned)
+                                                  const float *__restrict__ g, const float *__restrict__ p,
+                                                  long long n, float step, float m, int aligned)
 {
     const long long stride = (long long)gridDim.x * 256;
     const long long n4 = aligned ? n / 4 : 0;
     for (long long e4 = blockIdx.x * 256LL + threadIdx.x; e4 < n4; e4 += stride) {
-        const f4r yv = reinterpret_cast<const f4r *>(y)[e4], gv = reinterpret_cast<const f4r *>(g)[e4];
+        const f4r yv = reinterpret_cast<const f4r *>(y)[e4];
+        f4r gv = reinterpret_cast<const f4r *>(g)[e4];
+        if (p) gv *= reinterpret_cast<const f4r *>(p)[e4];
         const f4r cv = reinterpret_cast<const f4r *>(c)[e4];
         const f4r cn = yv - step * gv;
         reinterpret_cast<f4r *>(y)[e4] = cn + m * (cn - cv);
         reinterpret_cast<f4r *>(c)[e4] = cn;
     }
     for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
-        const float cn = fmaf(-step, g[e], y[e]);
+        const float gp = p ? g[e] * p[e] : g[e];
+        const float cn = fmaf(-step, gp, y[e]);
         y[e] = fmaf(m, cn - c[e], cn);
         c[e] = cn;
     }
 }
 
-hipError_t launch_nesterov(float *c, float *y, const float *g, long long n, float step, float m, hipStream_t st)
+hipError_t launch_nesterov(float *c, float *y, const float *g, const float *p, long long n, float step, float m,
+                           hipStream_t st)
 {
     const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(y) |
-                          reinterpret_cast<uintptr_t>(g)) & 15) == 0;
+                          reinterpret_cast<uintptr_t>(g) | reinterpret_cast<uintptr_t>(p)) & 15) == 0;
     const int blocks = (int)std::min<long long>((n / 4 + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_nesterov, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, y, g, n, step, m, aligned);
+    hipLaunchKernelGGL(k_nesterov, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, y, g, p, n, step, m, aligned);
     return hipGetLastError();
 }
 

@@ -345,10 +345,25 @@ class GradientDescent:
     + lam_lap sum (Lap c)^2 + huber_lam sum h_delta(c)."""
 
     def __init__(self, projector: Projector, step: float, nesterov: bool = False, lam_lap: float = 0.0,
-                 huber: tuple | None = None, loss_delta: float | None = None):
+                 huber: tuple | None = None, loss_delta: float | None = None,
+                 precond: torch.Tensor | None = None):
         self.P, self.step, self.nesterov = projector, float(step), bool(nesterov)
         self.lam_lap, self.huber = float(lam_lap), huber
         self.loss_delta = None if loss_delta is None else float(loss_delta)
+        if precond is not None:
+            _f32(precond, projector.vol_shape, "precond", projector.device)
+        self.precond = precond
+
+    @staticmethod
+    def voxel_preconditioner(projector: Projector, floor: float = 1e-6) -> torch.Tensor:
+        """Diagonal preconditioner 1 / (A^T A u)_{v,0} per voxel (all coefficients of a
+        voxel share it), u the unit isotropic field: the normal operator's scale at
+        each voxel, floored at floor times its maximum."""
+        u = torch.zeros(projector.vol_shape, device=projector.device)
+        u[..., 0] = 1.0
+        d = projector.adjoint(projector.forward(u))[..., :1]
+        d = d.clamp_min(floor * float(d.max()))
+        return (1.0 / d).expand(projector.vol_shape).contiguous()
 
     def objective_grad(self, c, data, w=None, mu=0.0, work=None):
         """(value float64[1], grad) of the whole objective at c."""
@@ -386,6 +401,7 @@ class GradientDescent:
             losses[k - 1:k].copy_(val)
             m = (k - 1.0) / (k + 2.0) if self.nesterov else 0.0
             call("tt_gd_step", C.c_void_p(c.data_ptr()), C.c_void_p(y.data_ptr()), C.c_void_p(grad.data_ptr()),
+                 C.c_void_p(self.precond.data_ptr()) if self.precond is not None else None,
                  c.numel(), self.step, m, _stream(c))
         return losses
 

@@ -100,3 +100,31 @@ def test_gradient_descent_huber_loss_parity():
     assert np.all(np.abs(losses - losses_ref) <= 1e-5 * np.abs(losses_ref))
     assert rel_l2(c.cpu().numpy(), c_ref) <= 1e-5
     assert losses[-1] < losses[0]
+
+
+def test_preconditioned_descent_parity():
+    """Diagonal voxel preconditioner 1 / (A^T A u)_{v,0}: the helper against the
+    oracle's construction, then 8 preconditioned Nesterov steps."""
+    w = synth.WORKLOADS["c1"]
+    og = oracle.Geometry.from_workload(w)
+    u = np.zeros(og.vol_shape)
+    u[..., 0] = 1.0
+    dref = oracle.adjoint(og, oracle.project(og, u))[..., :1]
+    dref = np.maximum(dref, 1e-6 * dref.max())
+    p_ref = np.broadcast_to(1.0 / dref, og.vol_shape).copy()
+    P = gpu_projector(og)
+    p_gpu = GradientDescent.voxel_preconditioner(P)
+    assert rel_l2(p_gpu.cpu().numpy(), p_ref) <= 1e-5
+    c_true = phantom.coefficients(w).astype(np.float64)
+    data = oracle.project(og, c_true).astype(np.float32).astype(np.float64)
+    mu = 1e-3
+    step = 0.4  # the preconditioned normal operator has unit scale on the support
+    c_ref, losses_ref = gradient_descent(og, np.zeros(og.vol_shape), data, step, 8, mu=mu, nesterov=True,
+                                         precond=p_ref.astype(np.float32).astype(np.float64))
+    c = torch.zeros(P.vol_shape, device=DEV)
+    gd = GradientDescent(P, step, nesterov=True, precond=torch.from_numpy(p_ref.astype(np.float32)).to(DEV))
+    losses = gd.run(c, torch.from_numpy(data.astype(np.float32)).to(DEV), None, mu, 8).cpu().numpy()
+    print("preconditioned gd", losses[0], losses[-1], "ref", losses_ref[-1])
+    assert np.all(np.abs(losses - losses_ref) <= 1e-5 * np.abs(losses_ref))
+    assert rel_l2(c.cpu().numpy(), c_ref) <= 1e-5
+    assert losses[-1] < losses[0]

@@ -119,9 +119,9 @@ def test_regulariser_argument_errors_without_device():
     assert lib.tt_huber_reg(p, 4, 0.0, 1.0, p, None, None) == -1
     assert lib.tt_huber_reg(p, -1, 0.1, 1.0, p, None, None) == -2
     assert lib.tt_huber_reg(None, 0, 0.1, 1.0, None, None, None) == 0
-    assert lib.tt_gd_step(p, p, None, 4, 0.1, 0.0, None) == -1
-    assert lib.tt_gd_step(p, p, p, 4, float("inf"), 0.0, None) == -1
-    assert lib.tt_gd_step(None, None, None, 0, 0.1, 0.0, None) == 0
+    assert lib.tt_gd_step(p, p, None, None, 4, 0.1, 0.0, None) == -1
+    assert lib.tt_gd_step(p, p, p, None, 4, float("inf"), 0.0, None) == -1
+    assert lib.tt_gd_step(None, None, None, None, 0, 0.1, 0.0, None) == 0
 
 
 def test_huber_loss_argument_errors_without_device():

@@ -127,3 +127,22 @@ def test_huber_loss_small_residuals_and_fd():
         cm[idx] -= h
         fd = (huber_loss(g, cp, data, delta, w)[0] - huber_loss(g, cm, data, delta, w)[0]) / (2 * h)
         assert abs(fd - grad[idx]) < 1e-5 * max(1.0, abs(grad[idx]))
+
+
+def test_preconditioned_descent_first_step_and_minimiser():
+    g, data = _small_problem()
+    mu = 0.5
+    A = dense_A(g).reshape(-1, int(np.prod(g.vol_shape)))
+    H = 2 * (A.T @ A + mu * np.eye(A.shape[1]))
+    c_star = np.linalg.solve(H, 2 * A.T @ data.ravel()).reshape(g.vol_shape)
+    rng = np.random.default_rng(9)
+    p = rng.uniform(0.5, 2.0, g.vol_shape)
+    Ph = np.sqrt(p.ravel())
+    step = 1.0 / np.linalg.eigvalsh(Ph[:, None] * H * Ph[None, :]).max()
+    c0 = np.zeros(g.vol_shape)
+    c1, _ = gradient_descent(g, c0, data, step, 1, mu=mu, precond=p)
+    _, grad0, _ = oracle.loss_grad(g, c0, data, None, mu)
+    assert np.abs(c1 - (c0 - step * p * grad0)).max() < 1e-14
+    c_long, losses = gradient_descent(g, c0, data, step, 3000, mu=mu, precond=p)
+    assert np.linalg.norm(c_long - c_star) / np.linalg.norm(c_star) < 1e-10
+    assert np.all(np.diff(losses) <= 1e-12 * losses[0])
