@@ -49,7 +49,7 @@ def algorithmic_bytes(w):
 
 
 def kernel_bytes(kind, w, n_unique, launches_per_call, S):
-    """Algorithmic bytes of one launch of a kernel class."""
+    """Algorithmic bytes of one launch of a kernel class (per-projection figures x projections per launch)."""
     V, C = w.n_vox, w.n_coeff
     img = 4.0 * w.nj * w.nk * w.n_seg
     if kind == "backproject":  # the whole adjoint of all S projections
@@ -312,7 +312,7 @@ def main():
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np

@@ -6,7 +6,7 @@ machine-learning models; here such data trains a small 3-D convolutional
 network that maps the normalised backprojection of the measured data to
 initial SH coefficients, which L-BFGS then refines.  Zero-initialised L-BFGS
 is the fallback (taken when the prediction does not lower the loss), and the
-final data residual is the judge.
+final data residual decides whether it helped.
 
 Pipeline (every numerical step runs in libtt_hip.so):
   1. x = A^T I / kappa, with kappa the median over the support of
