@@ -220,7 +220,7 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
             f.ejf[a] = (float)f.ej[a];
             f.ekf[a] = (float)f.ek[a];
             f.df[a] = (float)f.d[a];
-            f.inv_df[a] = (float)f.inv_d[a];
+            f.inv_df[a] = f.inv_d[a] != 0.0 ? (float)f.inv_d[a] : kFlatInv;
         }
         for (int c = 0; c < g.n_seg; ++c) {
             double *row = &B[((size_t)s * g.n_seg + c) * C];

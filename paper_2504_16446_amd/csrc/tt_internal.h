@@ -38,7 +38,11 @@ struct ProjFrame {
     // upper chain as (slope, intercept) pairs, hull[6..11] the lower chain).
     float hull[12];
     float ejf[3], ekf[3], df[3];  // float copies for the small offsets inside the cube
-    float inv_df[3];              // 1 / d_a or 0
+    // 1 / d_a, or kFlatInv when the ray is parallel to plane a: the adjoint's
+    // parameter range |P_a + tau d_a| < 1 then reads (-P_a - 1, -P_a + 1) *
+    // kFlatInv, which is all tau for |P_a| < 1 and empty otherwise, and some
+    // other axis (|d_b| >= 1/sqrt 3) always bounds the range.
+    float inv_df[3];
     // Slab plan of the LDS-staged march (tiles of kMarchTile x kMarchTile
     // rays): slabs are planes of axis slab_a (0 = x, 1 = y); each slab holds
     // the samples whose cell lies in slab_w consecutive planes, and stages a
@@ -58,6 +62,7 @@ struct ProjFrame {
     float jos_rj;
 };
 
+constexpr float kFlatInv = 1.0e30f;
 constexpr int kMarchTile = 16;  // rays per tile edge in the forward march
 
 int num_coeffs(int ell_max);

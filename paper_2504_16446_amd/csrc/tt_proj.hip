@@ -891,27 +891,25 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
                     for (int u4 = 0; u4 < UP / 4; ++u4) yv[u4] = yrow[k * (UP / 4) + u4];  // in flight meanwhile
                     const float dk = (float)(k - bi) - br;
                     const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
-                    // parameter range along the ray inside the open cube: |P_m + tau d_m| < 1 for every axis
-                    float tlo = -3.0e38f, thi = 3.0e38f;
+                    // parameter range along the ray inside the open cube: |P_m + tau d_m| < 1
+                    // for every axis (branch-free: see kFlatInv for rays parallel to a face)
+                    float tlo = fmaf(-P[0], f.inv_df[0], -hinv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) {
-                        if (f.inv_df[m] != 0.0f) {
-                            const float cm = -P[m] * f.inv_df[m];
-                            tlo = fmaxf(tlo, cm - hinv[m]);
-                            thi = fminf(thi, cm + hinv[m]);
-                        } else if (fabsf(P[m]) >= 1.0f) {
-                            thi = -3.0e38f;
-                        }
+                    for (int m = 1; m < 3; ++m) {
+                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], -hinv[m]));
+                        thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
                     }
                     float wsum = 0.0f;
                     if (tlo < thi) {
-                        // samples n with tau = n step - t inside (tlo, thi)
+                        // samples n with tau = n step - t inside (tlo, thi); there every
+                        // |P_m + tau d_m| < 1, so the tent factors need no clamp at 0
+                        // (a sample at the boundary gives a factor of rounding size)
                         const int m0 = (int)ceilf(tr + tlo * inv_stepf), m1 = (int)floorf(tr + thi * inv_stepf);
                         float tau = ((float)m0 - tr) * stepf;
                         for (int mm = m0; mm <= m1; ++mm) {
-                            const float wx = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[0], P[0])));
-                            const float wy = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[1], P[1])));
-                            const float wz = fmaxf(0.0f, 1.0f - fabsf(fmaf(tau, f.df[2], P[2])));
+                            const float wx = 1.0f - fabsf(fmaf(tau, f.df[0], P[0]));
+                            const float wy = 1.0f - fabsf(fmaf(tau, f.df[1], P[1]));
+                            const float wz = 1.0f - fabsf(fmaf(tau, f.df[2], P[2]));
                             wsum = fmaf(wx * wy, wz, wsum);
                             tau += stepf;
                         }

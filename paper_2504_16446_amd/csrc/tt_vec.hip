@@ -47,7 +47,9 @@ __device__ void block_sums(double (&acc)[NV], int nv, double *partials, int stri
 }
 
 // d = sum_a coef[a] b_a over masked a;  partials: d . b_a (a < nb) and d . d (index kMaxBasis).
-// float4 body over n / 4 elements, scalar tail.
+// One float per thread and step: every b_a value stays live until the dots
+// are formed, and with float4 steps those registers held the kernel to two
+// waves per SIMD and ~4.7 TB/s; scalar steps give four waves and ~6.5 TB/s.
 __global__ __launch_bounds__(256) void k_combine(VecList b, int nb, const double *__restrict__ coef,
                                                  const int *__restrict__ mask, long long n, float *__restrict__ d,
                                                  double *__restrict__ partials)
@@ -62,28 +64,8 @@ __global__ __launch_bounds__(256) void k_combine(VecList b, int nb, const double
         mk[a] = a < nb && mask[a];
         cf[a] = mk[a] ? (float)coef[a] : 0.0f;
     }
-    const long long n4 = n >> 2;
     const long long stride = (long long)gridDim.x * 256;
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n4; e += stride) {
-        f4 bv[kMaxBasis];
-        f4 dv = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int a = 0; a < kMaxBasis; ++a) {
-            bv[a] = f4{0.f, 0.f, 0.f, 0.f};
-            if (mk[a]) {
-                bv[a] = reinterpret_cast<const f4 *>(b.p[a])[e];
-                dv += cf[a] * bv[a];
-            }
-        }
-        reinterpret_cast<f4 *>(d)[e] = dv;
-#pragma unroll
-        for (int a = 0; a < kMaxBasis; ++a)
-            if (mk[a])
-                acc[a] += (double)dv.x * bv[a].x + (double)dv.y * bv[a].y + (double)dv.z * bv[a].z +
-                          (double)dv.w * bv[a].w;
-        acc[kMaxBasis] += (double)dv.x * dv.x + (double)dv.y * dv.y + (double)dv.z * dv.z + (double)dv.w * dv.w;
-    }
-    for (long long e = 4 * n4 + blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += stride) {
         float bv[kMaxBasis];
         float dv = 0.0f;
 #pragma unroll
