@@ -126,8 +126,8 @@ __global__ __launch_bounds__(256) void k_map_fp32(const float *__restrict__ c, c
 }
 
 // Register-resident variant for Cp <= 64 (ell_max <= 12): each wave keeps
-// its B operands for every k-step in registers, and the block walks voxel
-// tiles with a stride of the grid, prefetching the next tile's coefficients
+// its B operands for every k-step in registers, and the block walks a range
+// of consecutive voxel tiles, prefetching the next tile's coefficients
 // into registers while the current tile's MFMAs run, so coefficient loads,
 // MFMAs and the M stores of consecutive tiles overlap.
 constexpr int kCtStrideRb = 81;  // odd: the transposed tile writes hit distinct banks
@@ -171,9 +171,14 @@ __global__ __launch_bounds__(256) void k_map_fp32_rb(const float *__restrict__ c
             }
         }
     };
-    int tile = blockIdx.x;
-    if (tile < ntiles) prefetch(tile);
-    for (; tile < ntiles; tile += gridDim.x) {
+    // each block walks a contiguous range of tiles, so that its stores into
+    // every projection's M are one sequential stream (scattered 1 KiB pieces
+    // stall on DRAM write credits)
+    const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int tend = min(ntiles, (int)blockIdx.x * per + per);
+    int tile = blockIdx.x * per;
+    if (tile < tend) prefetch(tile);
+    for (; tile < tend; ++tile) {
         __syncthreads();  // the previous tile's LDS reads are done
 #pragma unroll
         for (int i = 0; i < NPF; ++i) {
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(256) void k_map_fp32_rb(const float *__restrict__ c
             }
         }
         __syncthreads();
-        if (tile + (int)gridDim.x < ntiles) prefetch(tile + gridDim.x);  // in flight during the MFMAs
+        if (tile + 1 < tend) prefetch(tile + 1);  // in flight during the MFMAs
         f4 acc[4][4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
