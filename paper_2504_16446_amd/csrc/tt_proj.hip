@@ -495,19 +495,40 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
             kz = fmin(kz, b00[2] + J * f.ej[2] + K * f.ek[2] + t * rZ);
         }
         const int plane = EB * EZ, nbox = (W + 1) * plane;
-        const float inv_plane = 1.0f / (float)plane, inv_ez = 1.0f / (float)EZ;
         // M strides (in voxels) of the box axes A and B; z is contiguous
         const int sy = nz + 2, sx = (ny + 2) * sy;
         const int sA = A == 0 ? sx : sy, sB = A == 0 ? sy : sx;
         const unsigned nAp = (A == 0 ? nx : ny) + 1, nBp = (A == 0 ? ny : nx) + 1, nZp = nz + 1;
         // LDS layout box[q][e]: the q-th float4 of all staged voxels, then the next
         const int da = plane, db = EZ, dz = 1;
+        // Staging walk: thread t stages box elements e = t + 256 i.  Its first
+        // element's (plane, row, z) and the step of 256 elements are decoded
+        // once; every later element follows by adds and two carries, and its M
+        // offset from the slab origin (in voxels, 32-bit) likewise.
+        const int e_pl = threadIdx.x / plane, e_r = threadIdx.x - e_pl * plane;
+        const int e_ib = e_r / EZ, e_iz = e_r - e_ib * EZ;
+        const int s_pl = 256 / plane, s_r = 256 - s_pl * plane;
+        const int s_ib = s_r / EZ, s_iz = s_r - s_ib * EZ;
+        const int s_off = s_pl * sA + s_ib * sB + s_iz;  // M offset of one step without carries
+        const int cz_off = sB - EZ, cb_off = sA - EB * sB;  // extra M offset of a z / row carry
+        // Samples in sample order m have index position q0 + m dq with dq_A > 0.
+        const int nstart = fwd ? n0 : n1;
+        double q0[3], dq[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q0[a] = fma((double)nstart, ds[a], b[a]);
+            dq[a] = fwd ? ds[a] : -ds[a];
+        }
+        const double inv_dqA = 1.0 / dq[A];  // |d_A| >= 1/4 for a planned projection
+        const float dqA = (float)dq[A], dqB = (float)dq[B], dqZ = (float)dq[2];
+        const float wmax = (float)(W - 1), bmax = (float)(EB - 2), zmax = (float)(EZ - 2);
         int m = 0;
         for (int A0 = amin; A0 <= amax; A0 += W) {
             const int B0 = (int)floor(fma((double)A0, rB, kb)) - 1, Z0 = (int)floor(fma((double)A0, rZ, kz)) - 1;
-            const long long org = (long long)A0 * sA + (long long)B0 * sB + Z0;  // may lie outside M
+            const f4 *src0 = reinterpret_cast<const f4 *>(Mp) + ((long long)A0 * sA + (long long)B0 * sB + Z0) * Q;
             __syncthreads();  // the previous slab's gathers are done
             constexpr int KB = 4;  // staged voxels per thread in flight
+            int pl = e_pl, ib = e_ib, iz = e_iz, off = e_pl * sA + e_ib * sB + e_iz;
             for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * KB) {
                 f4 v[KB][Q];
 #pragma unroll
@@ -515,15 +536,25 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
                     const int e = e0 + 256 * kk;
 #pragma unroll
                     for (int q = 0; q < Q; ++q) v[kk][q] = f4{0.f, 0.f, 0.f, 0.f};
-                    const int pl = (int)(((float)e + 0.5f) * inv_plane);
-                    const int r = e - pl * plane;
-                    const int ib = (int)(((float)r + 0.5f) * inv_ez);
-                    const int iz = r - ib * EZ;
                     if (e < nbox && (unsigned)(A0 + pl) <= nAp && (unsigned)(B0 + ib) <= nBp &&
                         (unsigned)(Z0 + iz) <= nZp) {
-                        const f4 *src = reinterpret_cast<const f4 *>(Mp + (org + pl * sA + ib * sB + iz) * UP);
 #pragma unroll
-                        for (int q = 0; q < Q; ++q) v[kk][q] = src[q];
+                        for (int q = 0; q < Q; ++q) v[kk][q] = src0[off * Q + q];
+                    }
+                    // advance by 256 elements
+                    pl += s_pl;
+                    ib += s_ib;
+                    iz += s_iz;
+                    off += s_off;
+                    if (iz >= EZ) {
+                        iz -= EZ;
+                        ++ib;
+                        off += cz_off;
+                    }
+                    if (ib >= EB) {
+                        ib -= EB;
+                        ++pl;
+                        off += cb_off;
                     }
                 }
 #pragma unroll
@@ -536,28 +567,33 @@ __global__ __launch_bounds__(256) void k_march(const float *__restrict__ M, cons
                 }
             }
             __syncthreads();
-            for (; m < count; ++m) {
-                const int n = fwd ? n0 + m : n1 - m;
-                const double pa = fma((double)n, ds[A], b[A]);
-                const int ia = (int)floor(pa);
-                if (ia >= A0 + W) break;  // belongs to a later slab
-                const double pb = fma((double)n, ds[B], b[B]);
-                const double pz = fma((double)n, ds[2], b[2]);
-                const int ibb = (int)floor(pb), izz = (int)floor(pz);
-                const float fa = (float)(pa - ia), fb = (float)(pb - ibb), fz = (float)(pz - izz);
-                const int la = min(max(ia - A0, 0), W - 1);
-                const int lbb = min(max(ibb - B0, 0), EB - 2);
-                const int lz = min(max(izz - Z0, 0), EZ - 2);
+            // samples of this slab: index position along A below A0 + W
+            int m_end = m;
+            if (m < count) m_end = min(count, max(m, (int)ceil((A0 + W - q0[A]) * inv_dqA)));
+            // positions relative to the box origin, in float32 (magnitudes of a
+            // few tens); the cell is clamped into the box and the fractions are
+            // taken against the clamped cell, so a sample that rounding puts
+            // on the far side of a slab face still interpolates correctly
+            const float ra = (float)(fma((double)m, dq[A], q0[A]) - A0);
+            const float rb = (float)(fma((double)m, dq[B], q0[B]) - B0);
+            const float rz = (float)(fma((double)m, dq[2], q0[2]) - Z0);
+            float mm = 0.0f;
+            for (; m < m_end; ++m, mm += 1.0f) {
+                const float pa = fmaf(mm, dqA, ra), pb = fmaf(mm, dqB, rb), pz = fmaf(mm, dqZ, rz);
+                const float la = fminf(fmaxf(floorf(pa), 0.0f), wmax);
+                const float lbb = fminf(fmaxf(floorf(pb), 0.0f), bmax);
+                const float lz = fminf(fmaxf(floorf(pz), 0.0f), zmax);
+                const float fa = pa - la, fb = pb - lbb, fz = pz - lz;
                 const float ga_ = 1.0f - fa, gb_ = 1.0f - fb, gz_ = 1.0f - fz;
                 const float w00 = ga_ * gb_, w01 = ga_ * fb, w10 = fa * gb_, w11 = fa * fb;
                 const float w[8] = {w00 * gz_, w00 * fz, w01 * gz_, w01 * fz, w10 * gz_, w10 * fz, w11 * gz_, w11 * fz};
-                const int off[8] = {0, dz, db, db + dz, da, da + dz, da + db, da + db + dz};
-                const int base = (la * EB + lbb) * EZ + lz;
+                const int off8[8] = {0, dz, db, db + dz, da, da + dz, da + db, da + db + dz};
+                const int base = __umul24(__umul24((int)la, EB) + (int)lbb, EZ) + (int)lz;
 #pragma unroll
                 for (int cc = 0; cc < 8; ++cc) {
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const f4 mv = box[q * nbox + base + off[cc]];
+                        const f4 mv = box[q * nbox + base + off8[cc]];
                         acc[4 * q + 0] = fmaf(w[cc], mv.x, acc[4 * q + 0]);
                         acc[4 * q + 1] = fmaf(w[cc], mv.y, acc[4 * q + 1]);
                         acc[4 * q + 2] = fmaf(w[cc], mv.z, acc[4 * q + 2]);
