@@ -214,6 +214,8 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
             f.jos_gj[1] = (float)gjC;
             f.jos_gk[0] = (float)gkB;
             f.jos_gk[1] = (float)gkC;
+            f.jos_igk[0] = std::fabs(gkB) > 1e-6 ? (float)(1.0 / gkB) : kFlatInv;
+            f.jos_igk[1] = std::fabs(gkC) > 1e-6 ? (float)(1.0 / gkC) : kFlatInv;
             f.jos_rj = (float)((std::fabs(gkB) + std::fabs(gkC)) / std::fabs(det));
         }
         for (int a = 0; a < 3; ++a) {

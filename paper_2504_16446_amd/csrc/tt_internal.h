@@ -25,6 +25,9 @@ struct Geometry {
 // Number of basis functions of a geometry (SH count or grid size).
 int basis_count(const Geometry &g);
 
+// Stand-in for 1 / 0 in branch-free parameter ranges (see ProjFrame::inv_df).
+constexpr float kFlatInv = 1.0e30f;
+
 // Ray frame of one projection, float64, in centred sample coordinates.
 // The ray through pixel (j, k) is o + j e_j + k e_k + t d.
 struct ProjFrame {
@@ -59,10 +62,10 @@ struct ProjFrame {
     int jos_a;
     float jos_w;
     float jos_gj[2], jos_gk[2];
+    float jos_igk[2];  // 1 / jos_gk, or kFlatInv where |jos_gk| <= 1e-6 (see inv_df)
     float jos_rj;
 };
 
-constexpr float kFlatInv = 1.0e30f;
 constexpr int kMarchTile = 16;  // rays per tile edge in the forward march
 
 int num_coeffs(int ell_max);

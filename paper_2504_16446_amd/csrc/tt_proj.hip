@@ -867,21 +867,13 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
             for (int j = jlo; j <= jhi; ++j) {
                 const float dj = (float)(j - ai) - ar;
                 const float eB = dj * gjB, eC = dj * gjC;
-                float lo = -3.0e38f, hi = 3.0e38f;
-                if (fabsf(gkB) > 1e-6f) {
-                    const float x1 = (-1.0f - eB) / gkB, x2 = (1.0f - eB) / gkB;
-                    lo = fmaxf(lo, fminf(x1, x2));
-                    hi = fminf(hi, fmaxf(x1, x2));
-                } else if (fabsf(eB) >= 1.0f) {
-                    hi = -3.0e38f;
-                }
-                if (fabsf(gkC) > 1e-6f) {
-                    const float x1 = (-1.0f - eC) / gkC, x2 = (1.0f - eC) / gkC;
-                    lo = fmaxf(lo, fminf(x1, x2));
-                    hi = fminf(hi, fmaxf(x1, x2));
-                } else if (fabsf(eC) >= 1.0f) {
-                    hi = -3.0e38f;
-                }
+                // dk range with |dk gk + e| < 1 on both in-plane axes, branch-free: a
+                // flat axis (kFlatInv) gives all dk or none, and the other axis is
+                // never flat, so a non-empty range is finite
+                const float xB1 = (-1.0f - eB) * f.jos_igk[0], xB2 = (1.0f - eB) * f.jos_igk[0];
+                const float xC1 = (-1.0f - eC) * f.jos_igk[1], xC2 = (1.0f - eC) * f.jos_igk[1];
+                const float lo = fmaxf(fminf(xB1, xB2), fminf(xC1, xC2));
+                const float hi = fminf(fmaxf(xB1, xB2), fmaxf(xC1, xC2));
                 if (!(lo < hi)) continue;
                 const int klo = max(0, bi + (int)ceilf(br + lo - 1e-4f));
                 const int khi = min(nk - 1, bi + (int)floorf(br + hi + 1e-4f));
