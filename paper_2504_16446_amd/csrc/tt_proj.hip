@@ -909,31 +909,39 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
             const int ai = (int)af, bi = (int)bf, ti = (int)tf;
             const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
             const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
+            // -|1/d| per axis, held in vector registers: the range fma below
+            // already reads 1/d from a scalar register, and a VOP3 takes one
+            float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
+            asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
             const float ljf = (float)f.lj;
             const int jlo = max(0, ai + (int)ceilf(ar - ljf)), jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
+            // hull intercepts shifted by this voxel's fraction br and the 1e-4 slack
+            const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
+            const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
+            const f4 *ys = reinterpret_cast<const f4 *>(yf + (long long)s * nj * nk * UP);
             for (int j = jlo; j <= jhi; ++j) {
                 // rays of this row that can meet the open cube around the voxel
                 const float dj = (float)(j - ai) - ar;
-                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, f.hull[1]), fmaf(f.hull[2], dj, f.hull[3])),
-                                         fmaf(f.hull[4], dj, f.hull[5]));
-                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, f.hull[7]), fmaf(f.hull[8], dj, f.hull[9])),
-                                         fmaf(f.hull[10], dj, f.hull[11]));
-                const int klo = max(0, bi + (int)ceilf(br + zmin - 1e-4f));
-                const int khi = min(nk - 1, bi + (int)floorf(br + zmax + 1e-4f));
+                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
+                                         fmaf(f.hull[4], dj, cu[2]));
+                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
+                                         fmaf(f.hull[10], dj, cl[2]));
+                const int klo = max(0, bi + (int)ceilf(zmin));
+                const int khi = min(nk - 1, bi + (int)floorf(zmax));
                 const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
-                const f4 *yrow = reinterpret_cast<const f4 *>(yf + ((long long)s * nj + j) * nk * UP);
-                for (int k = klo; k <= khi; ++k) {
+                const f4 *yrow = ys + __umul24(j, nk * (UP / 4));  // row offsets stay below 2^24 float4
+                float dk = (float)(klo - bi) - br;
+                for (int k = klo; k <= khi; ++k, dk += 1.0f) {
                     f4 yv[UP / 4];
 #pragma unroll
                     for (int u4 = 0; u4 < UP / 4; ++u4) yv[u4] = yrow[k * (UP / 4) + u4];  // in flight meanwhile
-                    const float dk = (float)(k - bi) - br;
                     const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
                     // parameter range along the ray inside the open cube: |P_m + tau d_m| < 1
                     // for every axis (branch-free: see kFlatInv for rays parallel to a face)
-                    float tlo = fmaf(-P[0], f.inv_df[0], -hinv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+                    float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
 #pragma unroll
                     for (int m = 1; m < 3; ++m) {
-                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], -hinv[m]));
+                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
                         thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
                     }
                     float wsum = 0.0f;
