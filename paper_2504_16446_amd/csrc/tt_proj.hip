@@ -944,20 +944,19 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
                         tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
                         thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
                     }
+                    // samples n with tau = n step - t inside (tlo, thi): n from m0 to m1
+                    // (none if the range is empty); there every |P_m + tau d_m| < 1, so
+                    // the tent factors need no clamp at 0 (a sample at the boundary
+                    // gives a factor of rounding size).  The loop runs on tau itself,
+                    // whose end is put half a step past the last sample.
                     float wsum = 0.0f;
-                    if (tlo < thi) {
-                        // samples n with tau = n step - t inside (tlo, thi); there every
-                        // |P_m + tau d_m| < 1, so the tent factors need no clamp at 0
-                        // (a sample at the boundary gives a factor of rounding size)
-                        const int m0 = (int)ceilf(tr + tlo * inv_stepf), m1 = (int)floorf(tr + thi * inv_stepf);
-                        float tau = ((float)m0 - tr) * stepf;
-                        for (int mm = m0; mm <= m1; ++mm) {
-                            const float wx = 1.0f - fabsf(fmaf(tau, f.df[0], P[0]));
-                            const float wy = 1.0f - fabsf(fmaf(tau, f.df[1], P[1]));
-                            const float wz = 1.0f - fabsf(fmaf(tau, f.df[2], P[2]));
-                            wsum = fmaf(wx * wy, wz, wsum);
-                            tau += stepf;
-                        }
+                    const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
+                    const float tend = (m1 - tr + 0.5f) * stepf;
+                    for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
+                        const float wx = 1.0f - fabsf(fmaf(tau, f.df[0], P[0]));
+                        const float wy = 1.0f - fabsf(fmaf(tau, f.df[1], P[1]));
+                        const float wz = 1.0f - fabsf(fmaf(tau, f.df[2], P[2]));
+                        wsum = fmaf(wx * wy, wz, wsum);
                     }
 #pragma unroll
                     for (int u4 = 0; u4 < UP; u4 += 4) {
