@@ -307,6 +307,8 @@ def main():
     ap.add_argument("--ttr-c5", action="store_true",
                     help="also run the 256^3 plain-vs-warm comparison to relative residual 1e-3 (minutes)")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision report")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the derived-quantity, Joseph and regulariser measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
@@ -422,11 +424,11 @@ def main():
     print("[bench] precision report ...", file=sys.stderr, flush=True)
     precision = None if args.no_precision else precision_report(dev)
     print("[bench] derived quantities ...", file=sys.stderr, flush=True)
-    props = None if args.no_precision else properties_bench(dev)
+    props = None if args.no_extras else properties_bench(dev)
     print("[bench] Joseph's method ...", file=sys.stderr, flush=True)
-    joseph = None if args.no_precision else joseph_bench(w, dev)
+    joseph = None if args.no_extras else joseph_bench(w, dev)
     print("[bench] regularisers ...", file=sys.stderr, flush=True)
-    regs = None if args.no_precision else regulariser_bench(dev)
+    regs = None if args.no_extras else regulariser_bench(dev)
 
     line = {
         "metric": "fwd+adj projector GB/s & % HBM roof; time-to-residual warm-start vs plain",
