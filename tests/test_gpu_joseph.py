@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from geoms import small, tilted_angles
+from geoms import degenerate, small, steep, tilted_angles
 from helpers import gpu_projector, rel_l2, rel_max
 from paper_2504_16446_amd import phantom, synth
 from paper_2504_16446_amd.projector import LBFGS, Projector
@@ -55,6 +55,8 @@ CASES = {
     "small_l8_seg16": lambda: _jos(small(ell_max=8, n_seg=16)),
     "half_circle": lambda: oracle.Geometry((9, 11, 10), 2, *tilted_angles(3, (0.0, 33.0)), 12, 10, 6,
                                            synth.lab_frame(), seg_span=np.pi, model="joseph"),
+    "steep_tilts": lambda: steep(model="joseph"),
+    "degenerate": lambda: degenerate(model="joseph"),
     "c1": lambda: oracle.Geometry.from_workload(synth.WORKLOADS["c1"], model="joseph"),
 }
 

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from geoms import small, tiny, workload
+from geoms import degenerate, small, steep, tiny, workload
 from helpers import gpu_projector, rel_l2, rel_max
 from paper_2504_16446_amd import synth
 
@@ -47,6 +47,8 @@ CASES = {
     "small_l6_seg8": lambda: small(ell_max=6),
     "small_l0": lambda: small(ell_max=0, n_seg=4),
     "half_circle_segments": _half_circle,   # no antipodal folding: 6 distinct segments
+    "steep_tilts": lambda: steep(),          # forward march gathers these rays from global memory
+    "degenerate": lambda: degenerate(),      # 1-voxel-thick volume, one detector row, 2 segments
     "c1": lambda: workload("c1"),
 }
 
