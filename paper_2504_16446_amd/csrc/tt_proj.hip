@@ -231,8 +231,17 @@ static hipError_t map_fp32_rb_t(const Dims &d, const float *c, const float *Bsw,
     const int V = d.nx * d.ny * d.nz;
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     const int gy = (np * UP + 255) / 256, ntiles = (V + 63) / 64;
-    // about eight resident blocks' worth of work per CU over all row groups
-    const int gx = std::max(1, std::min(ntiles, 2048 / gy));
+    // one resident round of blocks over all row groups (measured 3% faster
+    // than four rounds: fewer concurrent M store streams)
+    static const int resident = [] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_map_fp32_rb<UP, KS>, 256, 0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 512;
+        return std::max(1, per_cu * cus);
+    }();
+    const int gx = std::max(1, std::min(ntiles, resident / gy));
     hipLaunchKernelGGL((k_map_fp32_rb<UP, KS>), dim3(gx, gy), dim3(256), 0, st, c, Bsw, V, d.C, d.ny, d.nz, s0, np,
                        vol_pad, M);
     return hipGetLastError();
