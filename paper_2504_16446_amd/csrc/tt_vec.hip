@@ -408,11 +408,37 @@ static VecList make_list(const float *const *p, int n)
     return v;
 }
 
+// Blocks of one resident round of a streaming kernel on the current device
+// (fixed per kernel, so its partial sums stay deterministic).
+template <typename K>
+static int resident_blocks(K kern)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return kBlocks;
+    return std::max(1, per_cu * cus);
+}
+
+static int combine_blocks()
+{
+    static const int b = resident_blocks(k_combine);
+    return b;
+}
+
+static int multidot_blocks()
+{
+    static const int b = resident_blocks(k_multidot);
+    return b;
+}
+
 hipError_t lbfgs_combine(const float *const *basis, int nb, const double *coef, const int *mask, long long n,
                          float *d, double *partials, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_combine, dim3(kBlocks), dim3(256), 0, s, make_list(basis, nb), nb, coef, mask, n, d, partials);
-    hipLaunchKernelGGL(k_sum_columns, dim3(kMaxBasis + 1), dim3(256), 0, s, partials, kBlocks, kMaxBasis + 1, out);
+    const int nblk = combine_blocks();
+    hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(256), 0, s, make_list(basis, nb), nb, coef, mask, n, d, partials);
+    hipLaunchKernelGGL(k_sum_columns, dim3(kMaxBasis + 1), dim3(256), 0, s, partials, nblk, kMaxBasis + 1, out);
     return hipGetLastError();
 }
 
@@ -421,9 +447,10 @@ hipError_t lbfgs_multidot(const float *x, const float *const *vecs, int nv, cons
                           const int *ist, int gold)
 {
     VecList ys = y_slots ? make_list(y_slots, ns) : VecList{};
-    hipLaunchKernelGGL(k_multidot, dim3(kBlocks), dim3(256), 0, s, x, make_list(vecs, nv), nv, mask, n, partials, ys,
+    const int nblk = multidot_blocks();
+    hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(256), 0, s, x, make_list(vecs, nv), nv, mask, n, partials, ys,
                        y_slots ? ist : nullptr, gold);
-    hipLaunchKernelGGL(k_sum_columns, dim3(nv), dim3(256), 0, s, partials, kBlocks, kMaxBasis + 1, out);
+    hipLaunchKernelGGL(k_sum_columns, dim3(nv), dim3(256), 0, s, partials, nblk, kMaxBasis + 1, out);
     return hipGetLastError();
 }
 
@@ -472,6 +499,6 @@ hipError_t lbfgs_resid_update(const Dims &d, float *r, const float *q, const flo
     return hipGetLastError();
 }
 
-int lbfgs_blocks() { return kBlocks; }
+int lbfgs_blocks() { return std::max(kBlocks, std::max(combine_blocks(), multidot_blocks())); }
 
 }  // namespace tt
