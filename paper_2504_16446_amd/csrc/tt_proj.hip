@@ -858,6 +858,21 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
     float *Qw = Qs[wave];
     for (int s = 0; s < S; ++s) {
         const ProjFrame &f = frames[s];
+        // this projection's B_s^T operands, loaded now so that the gather below
+        // hides their latency (they are only read by the MFMAs at its end)
+        s4 avb[MT];
+        float avf[UP / 4][MT];
+        if constexpr (BF16) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                avb[mt] = BuT16[((long long)s * Cp + mt * 16 + (lane & 15)) * 4 + (lane >> 4)];
+        } else {
+            const float *Bs = Bu + (long long)s * UP * Cp;
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) avf[ks][mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+        }
         float q[UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) q[u] = 0.0f;
@@ -985,9 +1000,6 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
         // g tile += B_s^T (coefficients x u) * Q^T (u x voxels)
         if constexpr (BF16) {
             // K = 16 (u padded with zeros): A from BuT16[s][coefficient][u], B = Q rounded to bf16
-            s4 av[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) av[mt] = BuT16[((long long)s * Cp + mt * 16 + (lane & 15)) * 4 + (lane >> 4)];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 const float *qv = Qw + (nt * 16 + (lane & 15)) * (UP + 1);
@@ -998,20 +1010,16 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
                 bv.z = u0 + 2 < UP ? f2bf(qv[min(u0 + 2, UP - 1)]) : (short)0;
                 bv.w = u0 + 3 < UP ? f2bf(qv[min(u0 + 3, UP - 1)]) : (short)0;
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x16bf16(av[mt], bv, acc[mt][nt]);
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x16bf16(avb[mt], bv, acc[mt][nt]);
             }
         } else {
-            const float *Bs = Bu + (long long)s * UP * Cp;
 #pragma unroll
             for (int ks = 0; ks < UP / 4; ++ks) {
-                float av[MT];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) av[mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     float bv = Qw[(nt * 16 + (lane & 15)) * (UP + 1) + ks * 4 + (lane >> 4)];
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(av[mt], bv, acc[mt][nt]);
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(avf[ks][mt], bv, acc[mt][nt]);
                 }
             }
         }
