@@ -830,6 +830,13 @@ hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *dat
 // backproject: block = brick of 4 (x) x 8 (y) x 8 (z) voxels; wave w owns the
 // x-slice w (64 voxels = 4 column tiles of 16).  Loops over all projections.
 // ---------------------------------------------------------------------------
+// Q tile entry (u = 4 ks + lane / 16) of voxel column 16 nt + lane % 16 (row stride UP + 1)
+template <int UP>
+__device__ __forceinline__ float qw_at(const float *Qw, int nt, int ks, int lane)
+{
+    return Qw[(nt * 16 + (lane & 15)) * (UP + 1) + ks * 4 + (lane >> 4)];
+}
+
 template <int UP, int MT, bool BF16, bool JOS>
 __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ yf, const ProjFrame *__restrict__ frames,
                                                      const float *__restrict__ Bu, const s4 *__restrict__ BuT16, int S, int nx, int ny, int nz,
@@ -855,6 +862,23 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // float32 trilinear path with 8+ unique segments: the last KD of the KS
+    // k-steps of projection s's MFMA chain run at the top of projection s + 1,
+    // beside that projection's set-up arithmetic, so that no wave issues the
+    // whole chain at once (Q_s is still in the wave's LDS tile then)
+    constexpr int KS = UP / 4, KD = (BF16 || JOS) ? 0 : KS / 2, KE = KS - KD;
+    float pend[KD > 0 ? KD : 1][MT];
+    auto deferred_mfma = [&]() {
+#pragma unroll
+        for (int kd = 0; kd < KD; ++kd) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float bv = qw_at<UP>(Qs[wave], nt, KE + kd, lane);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(pend[kd][mt], bv, acc[mt][nt]);
+            }
+        }
+    };
     float *Qw = Qs[wave];
     for (int s = 0; s < S; ++s) {
         const ProjFrame &f = frames[s];
@@ -920,7 +944,9 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
                 }
             }
         }
-        if (!JOS && valid) {
+        if (!JOS && (KD > 0 || valid)) {
+            // (with deferred MFMAs evaluated for every lane, so that they share
+            // this block; lanes outside the volume visit no rows)
             // Voxel centre in the ray frame: detector coordinates (a, bb) and
             // the along-ray coordinate t / step, in float64 (magnitudes up to
             // the volume size), each split into an integer and a fraction in
@@ -938,7 +964,11 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
             float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
             asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
             const float ljf = (float)f.lj;
-            const int jlo = max(0, ai + (int)ceilf(ar - ljf)), jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
+            const int jlo = max(0, ai + (int)ceilf(ar - ljf));
+            const int jhi = valid ? min(nj - 1, ai + (int)floorf(ar + ljf)) : jlo - 1;
+            if constexpr (KD > 0) {
+                if (s > 0) deferred_mfma();
+            }
             // hull intercepts shifted by this voxel's fraction br and the 1e-4 slack
             const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
             const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
@@ -1014,16 +1044,23 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
             }
         } else {
 #pragma unroll
-            for (int ks = 0; ks < UP / 4; ++ks) {
+            for (int ks = 0; ks < KE; ++ks) {
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
-                    float bv = Qw[(nt * 16 + (lane & 15)) * (UP + 1) + ks * 4 + (lane >> 4)];
+                    const float bv = qw_at<UP>(Qw, nt, ks, lane);
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(avf[ks][mt], bv, acc[mt][nt]);
                 }
             }
+#pragma unroll
+            for (int kd = 0; kd < KD; ++kd)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) pend[kd][mt] = avf[KE + kd][mt];
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (KD > 0) {
+        if (S > 0) deferred_mfma();
     }
 
     // epilogue: lane holds rows (coefficients) 16 mt + 4 (lane/16) + r of voxel column 16 nt + lane % 16
