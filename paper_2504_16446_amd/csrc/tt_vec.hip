@@ -210,6 +210,51 @@ __global__ __launch_bounds__(256) void k_resid_update(float *__restrict__ r, con
     block_sums<2>(acc, 2, partials, 2);
 }
 
+// Same update for the common layout n_seg = 2 U = 2 UP (no padded unique
+// segments): each pixel's n_seg values are UP/2 float4 per half, and the fold
+// pairs segment u with u + U, in the same order as above.  Requires 16-byte
+// aligned r, q, w.
+template <int UP>
+__global__ __launch_bounds__(256) void k_resid_update_v(float *__restrict__ r, const float *__restrict__ q,
+                                                        const float *__restrict__ w, const double *__restrict__ st,
+                                                        long long npix, float step, float *__restrict__ yf,
+                                                        double *__restrict__ partials)
+{
+    constexpr int H = UP / 4;  // float4 per half pixel
+    const float alpha = q ? (float)st[kAlpha] : 0.0f;
+    double acc[2] = {0.0, 0.0};
+    for (long long px = blockIdx.x * 256LL + threadIdx.x; px < npix; px += (long long)gridDim.x * 256) {
+        f4 *rp = reinterpret_cast<f4 *>(r) + px * 2 * H;
+        const f4 *qp = q ? reinterpret_cast<const f4 *>(q) + px * 2 * H : nullptr;
+        const f4 *wp = w ? reinterpret_cast<const f4 *>(w) + px * 2 * H : nullptr;
+        f4 fold[H];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                f4 rv = rp[hh * H + i];
+                if (qp) {
+                    rv = f4{fmaf(alpha, qp[hh * H + i].x, rv.x), fmaf(alpha, qp[hh * H + i].y, rv.y),
+                            fmaf(alpha, qp[hh * H + i].z, rv.z), fmaf(alpha, qp[hh * H + i].w, rv.w)};
+                    rp[hh * H + i] = rv;
+                }
+                const f4 wv = wp ? wp[hh * H + i] : f4{1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    acc[0] += (double)wv[l] * (double)rv[l] * (double)rv[l];
+                    acc[1] += (double)rv[l] * (double)rv[l];
+                }
+                const f4 t = 2.0f * wv * rv;
+                fold[i] = hh == 0 ? t : fold[i] + t;
+            }
+        }
+        f4 *o = reinterpret_cast<f4 *>(yf + px * UP);
+#pragma unroll
+        for (int i = 0; i < H; ++i) o[i] = step * fold[i];
+    }
+    block_sums<2>(acc, 2, partials, 2);
+}
+
 // ---------------------------------------------------------------------------
 // Planner kernels (single thread, float64).
 // Basis index: s slot i -> i, y slot i -> ns + i, gradient -> 2 ns  (ns = m + 1).
@@ -480,6 +525,19 @@ hipError_t lbfgs_resid_update(const Dims &d, float *r, const float *q, const flo
                               double *partials, double *out, hipStream_t s)
 {
     const long long npix = (long long)d.S * d.nj * d.nk;
+    const bool vec = d.nseg == 2 * d.U && d.U == d.Up && (d.Up == 4 || d.Up == 8) &&
+                     ((reinterpret_cast<uintptr_t>(r) | reinterpret_cast<uintptr_t>(q) |
+                       reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(yf)) & 15) == 0;
+    if (vec) {
+        if (d.Up == 4)
+            hipLaunchKernelGGL(k_resid_update_v<4>, dim3(kBlocks), dim3(256), 0, s, r, q, w, st, npix, d.step, yf,
+                               partials);
+        else
+            hipLaunchKernelGGL(k_resid_update_v<8>, dim3(kBlocks), dim3(256), 0, s, r, q, w, st, npix, d.step, yf,
+                               partials);
+        hipLaunchKernelGGL(k_sum_columns, dim3(2), dim3(256), 0, s, partials, kBlocks, 2, out);
+        return hipGetLastError();
+    }
     switch (d.Up) {
     case 4:
         hipLaunchKernelGGL(k_resid_update<4>, dim3(kBlocks), dim3(256), 0, s, r, q, w, st, npix, d.nseg, d.U, d.step, yf,
