@@ -281,8 +281,8 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
  * difference Laplacian of every coefficient channel, zero outside the volume:
  * grad += 2 lambda Lap(Lap c); value[0] += lambda sum (Lap c)^2 if value is
  * not NULL.  work: device float [n], holds Lap c on return.  c, work and grad
- * must not overlap.  TT_EUNSUPPORTED if nz * C > 12288 (one z row is staged in
- * LDS). */
+ * must not overlap.  TT_EUNSUPPORTED if C > 1024 or nx * ny * nz > 2^31 - 1
+ * (z chunks of a row with their neighbours are staged in LDS). */
 int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambda, float *work, float *grad,
                      double *value, void *stream);
 /* Huber norm lambda sum h(c_e), h(x) = x^2 / (2 delta) for |x| <= delta and

@@ -833,8 +833,8 @@ int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambd
 {
     if (!c || !work || !grad) return fail(TT_EINVAL, "null pointer");
     if (nx < 1 || ny < 1 || nz < 1 || C < 1) return fail(TT_ESHAPE, "sizes must be >= 1");
-    if ((long long)nz * C > 12288 || (long long)nx * ny > 0x7fffffffLL)
-        return fail(TT_EUNSUPPORTED, "nz * C above 12288 or nx * ny above 2^31");
+    if (C > kLapMaxC || (long long)nx * ny * nz > 0x7fffffffLL)
+        return fail(TT_EUNSUPPORTED, "C above " + std::to_string(kLapMaxC) + " or nx * ny * nz above 2^31");
     if (!std::isfinite(lambda)) return fail(TT_EINVAL, "lambda must be finite");
     TT_HIP(launch_laplacian_reg(c, nx, ny, nz, C, lambda, work, grad, value, (hipStream_t)stream));
     return TT_OK;

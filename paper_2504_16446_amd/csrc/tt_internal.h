@@ -116,6 +116,7 @@ constexpr int kPropFields = 22;
 hipError_t launch_tensor_props(const float *c, long long nvox, int C, float *out, hipStream_t st);
 
 // Regularisers and the gradient-descent update (tt_reg.hip).
+constexpr int kLapMaxC = 1024;  // coefficients per voxel supported by the Laplacian
 hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lam, float *work, float *grad,
                                 double *value, hipStream_t st);
 hipError_t launch_huber_reg(const float *c, long long n, double delta, double lam, float *grad, double *value,

@@ -7,74 +7,71 @@
 
 namespace tt {
 
-// One block per (x, y) row of the coefficient volume c[x][y][z][C]: the row's
-// z * C floats are contiguous; the block stages its own row in LDS (for the
-// +-C z neighbours) and reads the four adjacent rows (x +- 1, y +- 1, zero
-// outside) as float4 streams when rows are 16-byte aligned.
+// One block per z-chunk of an (x, y) row of the coefficient volume
+// c[x][y][z][C]: the chunk's zc * C floats are contiguous; the block stages
+// them with one halo voxel on each side in LDS (for the +-C z neighbours,
+// zero outside the volume) and reads the four adjacent rows' same chunk
+// (x +- 1, y +- 1, zero outside) as float4 streams when rows are 16-byte
+// aligned.  A ~12 KiB chunk instead of a whole staged row lets eight blocks
+// share a CU.
 //   ACC = false: out = Lap(in), value += lam sum Lap(in)^2 (if value)
 //   ACC = true:  out += scale * Lap(in)
-constexpr int kLapRowMax = 12288;  // floats of one staged row (48 KiB)
+constexpr int kLapChunkFloats = 3072;  // target zc * C per block
 
 typedef float f4r __attribute__((ext_vector_type(4)));
 
 template <bool ACC>
 __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ in, int nx, int ny, int nz, int C,
-                                                   float *__restrict__ out, float scale, double lam,
+                                                   int zc, float *__restrict__ out, float scale, double lam,
                                                    double *__restrict__ value, int aligned)
 {
     __shared__ double ws[4];
-    __shared__ float rowc[kLapRowMax];
-    const int x = blockIdx.x / ny, y = blockIdx.x % ny;
-    const int row = nz * C;  // <= kLapRowMax (checked by the caller)
-    const long long base = ((long long)x * ny + y) * row;
+    extern __shared__ float rowc[];  // (zc + 2) C floats: voxels z0 - 1 .. z0 + zc
+    const int nzc = (nz + zc - 1) / zc;
+    const int chunk = blockIdx.x % nzc, rowi = blockIdx.x / nzc;
+    const int x = rowi / ny, y = rowi % ny;
+    const int z0 = chunk * zc, z1 = min(nz, z0 + zc);
+    const int len = (z1 - z0) * C;  // output floats of this block
+    const long long rowlen = (long long)nz * C;
+    const long long base = ((long long)x * ny + y) * rowlen + (long long)z0 * C;
     const float *r0 = in + base;
-    const long long sx = (long long)ny * row;
-    const float *nb[4] = {x > 0 ? r0 - sx : nullptr, x + 1 < nx ? r0 + sx : nullptr, y > 0 ? r0 - row : nullptr,
-                          y + 1 < ny ? r0 + row : nullptr};
-    const bool vec = aligned && (row & 3) == 0;  // every row starts 16-byte aligned
-    if (vec) {
-        for (int e4 = threadIdx.x; e4 < row / 4; e4 += 256)
-            reinterpret_cast<f4r *>(rowc)[e4] = reinterpret_cast<const f4r *>(r0)[e4];
-    } else {
-        for (int e = threadIdx.x; e < row; e += 256) rowc[e] = r0[e];
-    }
+    const long long sx = (long long)ny * rowlen;
+    const float *nb[4] = {x > 0 ? r0 - sx : nullptr, x + 1 < nx ? r0 + sx : nullptr, y > 0 ? r0 - rowlen : nullptr,
+                          y + 1 < ny ? r0 + rowlen : nullptr};
+    // rowc[C + e] = r0[e] for e in [-C, len + C), zero beyond the volume
+    const int lo = z0 > 0 ? -C : 0, hi = z1 < nz ? len + C : len;
+    for (int e = threadIdx.x - C; e < len + C; e += 256) rowc[C + e] = (e >= lo && e < hi) ? r0[e] : 0.0f;
     __syncthreads();
+    // z0 C is a multiple of 4 (zc is), so with 4 | nz C every chunk starts 16-byte aligned
+    const bool vec = aligned && (rowlen & 3) == 0;
+    const int n4 = vec ? len / 4 : 0;
     double ss = 0.0;
-    if (vec) {
-        for (int e4 = threadIdx.x; e4 < row / 4; e4 += 256) {
-            f4r acc = -6.0f * reinterpret_cast<const f4r *>(rowc)[e4];
+    for (int e4 = threadIdx.x; e4 < n4; e4 += 256) {
+        f4r acc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (nb[q]) acc += reinterpret_cast<const f4r *>(nb[q])[e4];
+        for (int l = 0; l < 4; ++l) acc[l] = rowc[C + 4 * e4 + l - C] + rowc[C + 4 * e4 + l + C] - 6.0f * rowc[C + 4 * e4 + l];
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const int e = 4 * e4 + l;
-                if (e >= C) acc[l] += rowc[e - C];
-                if (e + C < row) acc[l] += rowc[e + C];
-            }
-            f4r *o = reinterpret_cast<f4r *>(out + base) + e4;
-            if (ACC) {
-                *o = scale * acc + *o;
-            } else {
-                *o = acc;
+        for (int q = 0; q < 4; ++q)
+            if (nb[q]) acc += reinterpret_cast<const f4r *>(nb[q])[e4];
+        f4r *o = reinterpret_cast<f4r *>(out + base) + e4;
+        if (ACC) {
+            *o = scale * acc + *o;
+        } else {
+            *o = acc;
 #pragma unroll
-                for (int l = 0; l < 4; ++l) ss += (double)acc[l] * (double)acc[l];
-            }
+            for (int l = 0; l < 4; ++l) ss += (double)acc[l] * (double)acc[l];
         }
-    } else {
-        for (int e = threadIdx.x; e < row; e += 256) {
-            float acc = -6.0f * rowc[e];
+    }
+    for (int e = 4 * n4 + threadIdx.x; e < len; e += 256) {
+        float acc = rowc[e] + rowc[e + 2 * C] - 6.0f * rowc[C + e];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (nb[q]) acc += nb[q][e];
-            if (e >= C) acc += rowc[e - C];
-            if (e + C < row) acc += rowc[e + C];
-            if (ACC) {
-                out[base + e] = fmaf(scale, acc, out[base + e]);
-            } else {
-                out[base + e] = acc;
-                ss += (double)acc * (double)acc;
-            }
+        for (int q = 0; q < 4; ++q)
+            if (nb[q]) acc += nb[q][e];
+        if (ACC) {
+            out[base + e] = fmaf(scale, acc, out[base + e]);
+        } else {
+            out[base + e] = acc;
+            ss += (double)acc * (double)acc;
         }
     }
     if (!ACC && value) {
@@ -86,13 +83,15 @@ __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ in,
 hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lam, float *work, float *grad,
                                 double *value, hipStream_t st)
 {
-    const long long rows = (long long)nx * ny;
-    if (rows > 0x7fffffffLL || (long long)nz * C > kLapRowMax) return hipErrorNotSupported;
+    const int zc = std::max(4, (kLapChunkFloats / C) & ~3);  // multiple of 4
+    const long long blocks = (long long)nx * ny * ((nz + zc - 1) / zc);
+    if (blocks > 0x7fffffffLL || C > kLapMaxC) return hipErrorNotSupported;
+    const size_t lds = sizeof(float) * (size_t)(zc + 2) * C;
     const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(work) |
                           reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
-    hipLaunchKernelGGL(k_laplacian<false>, dim3((unsigned)rows), dim3(256), 0, st, c, nx, ny, nz, C, work, 0.0f, lam,
-                       value, aligned);
-    hipLaunchKernelGGL(k_laplacian<true>, dim3((unsigned)rows), dim3(256), 0, st, work, nx, ny, nz, C, grad,
+    hipLaunchKernelGGL(k_laplacian<false>, dim3((unsigned)blocks), dim3(256), lds, st, c, nx, ny, nz, C, zc, work,
+                       0.0f, lam, value, aligned);
+    hipLaunchKernelGGL(k_laplacian<true>, dim3((unsigned)blocks), dim3(256), lds, st, work, nx, ny, nz, C, zc, grad,
                        (float)(2.0 * lam), 0.0, nullptr, aligned);
     return hipGetLastError();
 }

@@ -116,6 +116,7 @@ def test_regulariser_argument_errors_without_device():
     assert lib.tt_laplacian_reg(None, 2, 2, 2, 1, 1.0, p, p, None, None) == -1
     assert lib.tt_laplacian_reg(p, 0, 2, 2, 1, 1.0, p, p, None, None) == -2
     assert lib.tt_laplacian_reg(p, 2, 2, 2, 1, float("nan"), p, p, None, None) == -1
+    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1025, 1.0, p, p, None, None) == -6  # more coefficients than supported
     assert lib.tt_huber_reg(p, 4, 0.0, 1.0, p, None, None) == -1
     assert lib.tt_huber_reg(p, -1, 0.1, 1.0, p, None, None) == -2
     assert lib.tt_huber_reg(None, 0, 0.1, 1.0, None, None, None) == 0
