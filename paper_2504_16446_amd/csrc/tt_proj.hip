@@ -367,8 +367,11 @@ hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bsw16,
 
 // ---------------------------------------------------------------------------
 // march: one thread per ray; block = 16 (j) x 16 (k) rays of one projection.
-// Positions are float64 in padded index coordinates (voxel ix sits at ix + 1,
-// borders of M are zero), so no bounds test is needed inside the loop.
+// Ray positions are set up in float64 in padded index coordinates (voxel ix
+// sits at ix + 1, borders of M are zero), so no bounds test is needed inside
+// the loop.  The staged path computes each slab's sample count and first
+// position in float64 and steps its samples in float32 relative to the
+// staged box; the global path steps in float64.
 //
 // The tile's rays are marched slab by slab: a slab is W planes of the
 // horizontal axis A most aligned with the rays.  Before each slab the block
