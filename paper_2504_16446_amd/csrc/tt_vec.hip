@@ -272,20 +272,26 @@ __device__ void valid_list(const int *ist, int ns, int *idx, int &nidx)
     idx[nidx++] = 2 * ns;
 }
 
-__global__ void k_plan_direction(double *st, int *ist, int m)
+// The block stages the Gram matrix in LDS; thread 0 then runs the recursion
+// (each step depends on the previous one) on LDS operands.
+__global__ __launch_bounds__(64) void k_plan_direction(double *st, int *ist, int m)
 {
+    __shared__ double G[kMaxBasis * kMaxBasis];
+    __shared__ double del[kMaxBasis];
+    __shared__ int idx[kMaxBasis];
+    for (int e = threadIdx.x; e < kMaxBasis * kMaxBasis; e += blockDim.x) G[e] = st[kGram + e];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const int ns = m + 1, nb = 2 * ns + 1, gi = 2 * ns;
-    int idx[kMaxBasis];
     int nidx;
     valid_list(ist, ns, idx, nidx);
-    double del[kMaxBasis];
     for (int a = 0; a < nb; ++a) del[a] = 0.0;
     del[gi] = 1.0;
     const int cnt = ist[kCount];
     for (int t = cnt - 1; t >= 0; --t) {
         const int i = ist[kOrder + t];
         double v = 0.0;
-        for (int q = 0; q < nidx; ++q) v += del[idx[q]] * Gm(st, i, idx[q]);
+        for (int q = 0; q < nidx; ++q) v += del[idx[q]] * G[i * kMaxBasis + idx[q]];
         const double al = st[kRho + i] * v;
         st[kAlphaTmp + i] = al;
         del[ns + i] -= al;
@@ -295,7 +301,7 @@ __global__ void k_plan_direction(double *st, int *ist, int m)
     for (int t = 0; t < cnt; ++t) {
         const int i = ist[kOrder + t];
         double v = 0.0;
-        for (int q = 0; q < nidx; ++q) v += del[idx[q]] * Gm(st, ns + i, idx[q]);
+        for (int q = 0; q < nidx; ++q) v += del[idx[q]] * G[(ns + i) * kMaxBasis + idx[q]];
         const double be = st[kRho + i] * v;
         del[i] += st[kAlphaTmp + i] - be;
     }
@@ -424,7 +430,7 @@ __global__ void k_plan_update(double *st, int *ist, int m, double mu)
 // ---------------------------------------------------------------------------
 hipError_t lbfgs_plan_direction(double *st, int *ist, int m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_plan_direction, dim3(1), dim3(1), 0, s, st, ist, m);
+    hipLaunchKernelGGL(k_plan_direction, dim3(1), dim3(64), 0, s, st, ist, m);
     return hipGetLastError();
 }
 
