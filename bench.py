@@ -87,7 +87,7 @@ def cpu_baseline(w, n_sample, c_np, y_np):
     """FP64 oracle forward + adjoint on n_sample evenly spaced projections."""
     import numpy as np
     import oracle
-    from paper_2504_16446_amd import synth
+    import tt_inputs as synth
 
     inner, outer = synth.angles(w)
     sel = np.linspace(0, len(inner) - 1, n_sample).round().astype(int)
@@ -118,7 +118,8 @@ def warm_vs_plain_heldout(dev, n=4, plain_iters=30):
     residual the zero start reaches after plain_iters iterations (medians)."""
     import numpy as np
     import torch
-    from paper_2504_16446_amd import synth, warmstart
+    import tt_inputs as synth
+    from paper_2504_16446_amd import warmstart
     from paper_2504_16446_amd.projector import LBFGS, Projector
 
     if not os.path.exists(warmstart.DEFAULT_WEIGHTS):
@@ -165,7 +166,8 @@ def precision_report(dev, n_rays=128, n_vox=16):
     import numpy as np
     import torch
     import oracle
-    from paper_2504_16446_amd import phantom, synth
+    import tt_inputs as synth
+    from paper_2504_16446_amd import phantom
     from paper_2504_16446_amd.projector import Projector
 
     w = synth.WORKLOADS["c3"]
@@ -197,7 +199,7 @@ def properties_bench(dev, reps=5):
     """Derived per-voxel quantities on a 256^3 / ell_max 8 coefficient volume:
     HBM throughput (read C floats, write 22 floats per voxel) of one launch."""
     import torch
-    from paper_2504_16446_amd import synth
+    import tt_inputs as synth
     from paper_2504_16446_amd.projector import PROPERTY_FIELDS, tensor_properties
 
     w = synth.WORKLOADS["c5"]
@@ -228,7 +230,7 @@ def regulariser_bench(dev, reps=5):
     Laplacian 20 n, Huber 12 n, update 20 n for n floats)."""
     import ctypes as C
     import torch
-    from paper_2504_16446_amd import synth
+    import tt_inputs as synth
     from paper_2504_16446_amd._lib import call
     from paper_2504_16446_amd.projector import huber_reg, laplacian_reg
 
@@ -320,7 +322,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2504_16446_amd import phantom, synth
+    import tt_inputs as synth
+    from paper_2504_16446_amd import phantom
     from paper_2504_16446_amd.projector import LBFGS, Projector
 
     w = synth.WORKLOADS[args.workload]

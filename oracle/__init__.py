@@ -147,7 +147,7 @@ class Geometry:
 
     @classmethod
     def from_workload(cls, w, **kw):
-        from paper_2504_16446_amd import synth
+        import tt_inputs as synth
         inner, outer = synth.angles(w)
         args = dict(n=w.n, ell_max=w.ell_max, inner=inner, outer=outer, nj=w.nj, nk=w.nk,
                     n_seg=w.n_seg, frame=synth.lab_frame(), n_sub=w.n_sub, step=w.step)

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 from . import Geometry, project, sh
 

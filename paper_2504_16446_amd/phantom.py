@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import synth
+import tt_inputs as synth
 from .projector import sh_eval
 
 

@@ -11,7 +11,9 @@ import math
 import numpy as np
 import torch
 
-from . import _lib, synth
+import tt_inputs as synth
+
+from . import _lib
 from ._lib import Geometry, call, lib
 
 __all__ = ["Projector", "ProjectFn", "project", "LBFGS", "sh_eval", "num_coeffs", "tensor_properties",

@@ -41,7 +41,9 @@ import time
 import numpy as np
 import torch
 
-from . import net, synth
+import tt_inputs as synth
+
+from . import net
 from ._lib import call
 from .projector import LBFGS, Projector, sh_eval
 

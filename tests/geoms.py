@@ -2,7 +2,7 @@
 import numpy as np
 
 import oracle
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 
 def tilted_angles(n_rot, tilts_deg, span_deg=180.0, phase_deg=7.0):

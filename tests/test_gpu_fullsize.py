@@ -13,7 +13,8 @@ import torch
 
 import oracle
 from helpers import rel_l2
-from paper_2504_16446_amd import phantom, synth
+import tt_inputs as synth
+from paper_2504_16446_amd import phantom
 from paper_2504_16446_amd.projector import Projector
 
 pytestmark = pytest.mark.gpu

@@ -12,7 +12,8 @@ import torch
 import oracle
 from geoms import degenerate, small, steep, tilted_angles
 from helpers import gpu_projector, rel_l2, rel_max
-from paper_2504_16446_amd import phantom, synth
+import tt_inputs as synth
+from paper_2504_16446_amd import phantom
 from paper_2504_16446_amd.projector import LBFGS, Projector
 
 pytestmark = pytest.mark.gpu

@@ -14,7 +14,7 @@ import oracle
 from oracle import phantom
 from geoms import small, workload
 from helpers import gpu_projector, rel_l2
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 from paper_2504_16446_amd.projector import LBFGS
 
 pytestmark = pytest.mark.gpu

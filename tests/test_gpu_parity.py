@@ -12,7 +12,7 @@ import torch
 import oracle
 from geoms import degenerate, small, steep, tiny, workload
 from helpers import gpu_projector, rel_l2, rel_max
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"

@@ -17,7 +17,7 @@ import torch
 
 import oracle
 from oracle.derived import FIELDS, tensor_properties as oracle_props
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 from paper_2504_16446_amd.projector import PROPERTY_FIELDS, tensor_properties
 
 pytestmark = pytest.mark.gpu

@@ -13,7 +13,8 @@ import torch
 import oracle
 from helpers import gpu_projector, rel_l2
 from oracle.regularizers import gradient_descent, huber_reg as o_huber, laplacian, laplacian_reg as o_lap
-from paper_2504_16446_amd import phantom, synth
+import tt_inputs as synth
+from paper_2504_16446_amd import phantom
 from paper_2504_16446_amd.projector import GradientDescent, huber_reg, laplacian_reg
 
 pytestmark = pytest.mark.gpu

@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2504_16446_amd import net, synth, warmstart
+import tt_inputs as synth
+from paper_2504_16446_amd import net, warmstart
 from paper_2504_16446_amd._lib import call
 
 pytestmark = pytest.mark.gpu

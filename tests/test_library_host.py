@@ -95,6 +95,17 @@ def test_product_never_imports_oracle():
                 assert "tt_oracle" not in text, f
 
 
+def test_oracle_never_imports_product():
+    # the oracle shares only the seeded input generators (tt_inputs) with the product
+    for dirpath, _, files in os.walk(os.path.join(ROOT, "oracle")):
+        for f in files:
+            if f.endswith((".py", ".c", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "paper_2504_16446_amd" not in text and "libtt_hip" not in text, f
+    text = open(os.path.join(ROOT, "tt_inputs.py")).read()
+    assert "paper_2504_16446_amd" not in text and "import oracle" not in text
+
+
 def test_tensor_properties_argument_errors_without_device():
     lib = _lib().lib()
     buf = (C.c_float * 64)()
@@ -150,7 +161,7 @@ def test_create_rejects_orders_above_twelve_without_device():
 
 @pytest.mark.parametrize("basis,width", [("gk", 0.35), ("nn", None)])
 def test_kernel_basis_matrix_matches_oracle(basis, width):
-    from paper_2504_16446_amd import synth as _s
+    import tt_inputs as _s
     dirs = _s.hemisphere_dirs(20) if basis == "gk" else _s.truncated_icosahedron_dirs()
     og = oracle.Geometry((6, 7, 5), 0, *geoms_tilted(), 9, 8, 8, _s.lab_frame(), basis=basis, dirs=dirs,
                          width=width)

@@ -15,7 +15,7 @@ import numpy as np
 
 import oracle
 from geoms import tilted_angles
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 
 def _geom(basis, dirs, width=None, n=(6, 7, 5), n_seg=8, model="trilinear"):

@@ -14,7 +14,7 @@ from numpy.polynomial import legendre as npleg
 
 import oracle
 from geoms import small, workload
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 

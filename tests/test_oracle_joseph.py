@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 
 def _geom(n, ell_max, inner_deg, outer_deg, nj, nk, n_seg=8, **kw):

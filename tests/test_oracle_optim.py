@@ -14,7 +14,7 @@ import pytest
 import oracle
 from oracle import dense, phantom
 from geoms import small, tiny, workload
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 
 def _problem(g, seed=12):

@@ -15,7 +15,7 @@ import pytest
 import oracle
 from oracle import dense
 from geoms import small, tiny, workload
-from paper_2504_16446_amd import synth
+import tt_inputs as synth
 
 SQ4PI = math.sqrt(4 * math.pi)
 

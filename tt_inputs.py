@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs shared by the GPU path, the tests and the benchmark.
+"""Seeded synthetic inputs shared by the GPU path, the oracle, the tests and the benchmark.
 
 This module draws random numbers and lays out workload configurations only.
 It holds none of the tensor-tomography arithmetic (no rotations of the
