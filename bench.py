@@ -3,17 +3,27 @@
 
 One step = one L-BFGS iteration of the plain method (search direction from
 the history, forward projection of the direction, exact line search,
-coefficient/residual update, adjoint for the new gradient, history update)
-on the 100^3, ell_max 8, 240-projection, 100x100 x 8-segment workload with a
-seeded twisted-fibre phantom and 1% noise.  Inputs are resident on the
-device before the timed region.
+coefficient/residual update, adjoint for the new gradient, history update).
+Default workload: 256^3 voxels, ell_max 8 (45 coefficients), 400 projections,
+256x256 px x 16 segments, seeded multi-bundle phantom, no noise (the largest
+single-GPU configuration).  Inputs are resident on the device before the
+timed region.
 
 value = algorithmic bytes of one forward plus one adjoint (per projection
-4 C V + 4 nj nk n_seg each way) per step, divided by the step time.
+4 C V + 4 nj nk n_seg each way) per step, divided by the step time (an
+effective rate: the kernels keep data on chip across projections).
 
-Also reported: the dominant kernel against the HBM roofline (HIP-event
-timing of every launch inside the timed region), the plain method's
-time-to-residual, and the float64 CPU oracle timed on a bounded sample.
+roofline: the dominant kernel against the roof that binds it -- the adjoint
+(voxel-driven gather + MFMA transpose map) against the fp32 compute peak with
+its algorithmic flops (16 U flops per ray sample touching the volume: 8
+voxels x U segment values x multiply-add; 2 U C flops per voxel and
+projection for the transpose map), the map against the fp32 MFMA peak, the
+march against HBM with its algorithmic bytes; HIP-event timing of every
+launch inside the timed region, measured HBM traffic from committed
+rocprofv3 counter runs.  Also reported: time to residual (at 256^3 the plain
+zero start against the learned warm start, both to relative residual 1e-3),
+the float64 CPU oracle on a bounded projection subset, precision tiers and
+secondary kernels.
 """
 from __future__ import annotations
 
@@ -30,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP32_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (and fp32 dense MFMA)
 
 
 def _cpu_model():
@@ -48,19 +59,28 @@ def algorithmic_bytes(w):
     return 4.0 * w.n_coeff * w.n_vox + 4.0 * w.nj * w.nk * w.n_seg
 
 
-def kernel_bytes(kind, w, n_unique, launches_per_call, S):
-    """Algorithmic bytes of one launch of a kernel class (per-projection figures x projections per launch)."""
-    V, C = w.n_vox, w.n_coeff
+def kernel_roof(kind, w, n_unique, samples, launches_per_step, avg_s):
+    """Roofline entry of one kernel class: (bound, algorithmic quantity per launch, unit, peak)."""
+    V, C, S = w.n_vox, w.n_coeff, w.n_proj
     img = 4.0 * w.nj * w.nk * w.n_seg
-    if kind == "backproject":  # the whole adjoint of all S projections
-        return S * (4.0 * C * V + img)
-    if kind == "march":        # np projections per launch: read the mapped volume, write the image
-        np_ = S / launches_per_call
-        return np_ * (4.0 * n_unique * V + img)
-    if kind == "map":          # read the volume once, write np mapped volumes
-        np_ = S / launches_per_call
-        return 4.0 * C * V + np_ * 4.0 * n_unique * V
+    per_launch_proj = S / launches_per_step
+    if kind == "backproject":  # the whole adjoint of all S projections per launch
+        flops = 16.0 * n_unique * samples + 2.0 * n_unique * C * V * S
+        return {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "algorithmic_flops_per_launch": flops,
+                "count": "16 U per ray sample touching the volume + 2 U C per voxel and projection"}
+    if kind == "map":  # read c once, M_s = B_s c for the batch's projections on MFMA
+        flops = 2.0 * n_unique * C * V * per_launch_proj
+        return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "algorithmic_flops_per_launch": flops, "count": "2 U C per voxel and projection"}
+    if kind == "march":  # read the batch's mapped volumes, write its images
+        nbytes = per_launch_proj * (4.0 * n_unique * V + img)
+        return {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "algorithmic_bytes_per_launch": nbytes, "count": "4 U V + 4 nj nk n_seg per projection"}
     return None
+
+
+WORKLOAD_LABEL = {"c1": "32cubed", "c2": "100cubed", "c3": "128cubed", "c4": "48cubed", "c5": "256cubed"}
 
 
 def _source_sha():
@@ -75,6 +95,8 @@ def _traffic(kernel, workload):
     """Measured HBM bytes per launch from committed rocprofv3 counter runs, if current."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
     if not os.path.exists(path):
+        path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{WORKLOAD_LABEL.get(workload, workload)}.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
@@ -83,19 +105,26 @@ def _traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, n_sample, c_np, y_np):
-    """FP64 oracle forward + adjoint on n_sample evenly spaced projections."""
+def cpu_sample_index(w, n_sample):
+    import numpy as np
+    return np.linspace(0, w.n_proj - 1, n_sample).round().astype(int)
+
+
+def cpu_baseline(w, n_sample, c_np, y_sel):
+    """FP64 oracle forward + adjoint on n_sample evenly spaced projections
+    (y_sel: the data of those projections); the rate extrapolates linearly in
+    the number of projections (projector cost is linear in S)."""
     import numpy as np
     import oracle
     import tt_inputs as synth
 
     inner, outer = synth.angles(w)
-    sel = np.linspace(0, len(inner) - 1, n_sample).round().astype(int)
+    sel = cpu_sample_index(w, n_sample)
     g = oracle.Geometry(w.n, w.ell_max, inner[sel], outer[sel], w.nj, w.nk, w.n_seg,
                         synth.lab_frame(), n_sub=w.n_sub, step=w.step)
     g.B()
     c64 = c_np.astype(np.float64)
-    y64 = y_np[sel].astype(np.float64)
+    y64 = np.asarray(y_sel, dtype=np.float64)
     t0 = time.perf_counter()
     oracle.project(g, c64)
     oracle.adjoint(g, y64)
@@ -107,7 +136,8 @@ def cpu_baseline(w, n_sample, c_np, y_np):
     return {
         "value": bytes_ / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
         "sample": (f"float64 C oracle, forward + adjoint of {n_sample} of {w.n_proj} projections "
-                   f"({w.name} geometry, same algorithmic-byte count per projection), {dt:.2f} s wall; "
+                   f"({w.name} geometry, same algorithmic-byte count per projection; the rate extrapolates "
+                   f"linearly to all {w.n_proj}), {dt:.2f} s wall; "
                    f"forward on {threads} OpenMP threads, adjoint on {adj_threads}; host '{_cpu_model()}', "
                    f"os.cpu_count()={os.cpu_count()}"),
     }
@@ -301,13 +331,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--ttr-iters", type=int, default=None,
-                    help="plain L-BFGS iterations for time-to-residual (default: the workload's)")
-    ap.add_argument("--cpu-sample", type=int, default=24, help="projections in the CPU-oracle sample")
+                    help="plain L-BFGS iterations for time-to-residual on workloads other than c5 (default 50)")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="projections in the CPU-oracle sample (default 4 at 256^3, 24 otherwise)")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start comparison")
-    ap.add_argument("--ttr-c5", action="store_true",
-                    help="also run the 256^3 plain-vs-warm comparison to relative residual 1e-3 (minutes)")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision report")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the derived-quantity, Joseph and regulariser measurements")
@@ -342,13 +371,17 @@ def main():
         del src, dst
 
     P = Projector.from_workload(w, device=dev)
+    samples = P.ray_samples()
+    forward_batch = P.batch
     c_true_np = phantom.coefficients(w)
     c_true = torch.from_numpy(c_true_np).to(dev)
-    clean = P.forward(c_true)
-    sigma = w.noise * float(clean.abs().max())
-    noise = torch.from_numpy(synth.noise(P.data_shape, w.seed_noise).astype(np.float32)).to(dev)
-    data = (clean + sigma * noise).contiguous()
-    del clean, noise
+    data = P.forward(c_true)
+    if w.noise > 0:
+        sigma = w.noise * float(data.abs().max())
+        noise = torch.from_numpy(synth.noise(P.data_shape, w.seed_noise).astype(np.float32)).to(dev)
+        data.add_(noise, alpha=sigma)
+        del noise
+    del c_true
     torch.cuda.synchronize()
 
     # ---- timed region: K L-BFGS iterations -------------------------------
@@ -382,48 +415,56 @@ def main():
         if n:
             kernels[k] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
                           "avg_launch_ms": ms / n}
-    dom = max(((k, v) for k, v in kernels.items() if k in ("map", "march", "backproject")),
-              key=lambda kv: kv[1]["ms_per_step"])[0]
-    per_call = kernels[dom]["launches_per_step"]
-    kb = kernel_bytes(dom, w, P.n_unique, per_call, w.n_proj)
-    avg_s = kernels[dom]["avg_launch_ms"] * 1e-3
-    achieved = kb / avg_s / 1e9
-    traffic = _traffic(dom, w.name)
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": traffic, "algorithmic_bytes_per_launch": kb}
+    roofs = {}
+    for k in ("map", "march", "backproject"):
+        if k in kernels:
+            r = kernel_roof(k, w, P.n_unique, samples, kernels[k]["launches_per_step"],
+                            kernels[k]["avg_launch_ms"] * 1e-3)
+            r["frac"] = r["achieved"] / r["peak"]
+            r["avg_launch_ms"] = kernels[k]["avg_launch_ms"]
+            r["traffic"] = _traffic(k, w.name)
+            roofs[k] = r
+    dom = max(roofs, key=lambda k: kernels[k]["ms_per_step"])
+    roofline = dict(kernel=dom, **roofs[dom])
 
-    # ---- plain method: time to residual ----------------------------------
-    iters = args.ttr_iters if args.ttr_iters is not None else (50 if w.name == "c2" else 10)
-    solver2 = LBFGS(P, m=10)
-    c2 = torch.zeros(P.vol_shape, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver2.init(c2, data, None, w.mu)
-    n_done, hist = solver2.run(iters)
-    torch.cuda.synchronize()
-    ttr_s = time.perf_counter() - t0
-    r = P.forward(c2) - data
-    final_rel = float(r.double().norm() / data.double().norm())
-    del solver2, r
-    ttr = {"plain": {"workload": w.name, "iterations": n_done, "seconds": ttr_s, "final_rel_residual": final_rel,
-                     "loss_first_last": [float(hist[0, 0]), float(hist[-1, 0])] if n_done else None},
-           "warm_start": None}
+    # ---- time to residual ---------------------------------------------------
+    ttr = {}
     del solver
+    n_sample = args.cpu_sample if args.cpu_sample is not None else (4 if w.name == "c5" else 24)
+    y_sel = data[torch.from_numpy(cpu_sample_index(w, n_sample)).to(dev)].cpu().numpy()
+    torch.cuda.empty_cache()
+    if w.name == "c5":
+        if not args.no_warm:
+            from paper_2504_16446_amd import warmstart
+            P = data = c = None
+            torch.cuda.empty_cache()
+            print("[bench] 256^3 plain vs warm start to relative residual 1e-3 ...", file=sys.stderr, flush=True)
+            model = warmstart.load(warmstart.DEFAULT_WEIGHTS, dev)
+            ttr["c5_plain_vs_warm"] = warmstart.compare(model, w, 1e-3, 1500)
+    else:
+        iters = args.ttr_iters if args.ttr_iters is not None else 50
+        solver2 = LBFGS(P, m=10)
+        c2 = torch.zeros(P.vol_shape, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver2.init(c2, data, None, w.mu)
+        n_done, hist = solver2.run(iters)
+        torch.cuda.synchronize()
+        ttr_s = time.perf_counter() - t0
+        solver2.refresh()
+        _, rn, In, _ = solver2.query()
+        ttr["plain"] = {"workload": w.name, "iterations": n_done, "seconds": ttr_s, "final_rel_residual": rn / In,
+                        "loss_first_last": [float(hist[0, 0]), float(hist[-1, 0])] if n_done else None}
+        del solver2, c2
+        if not args.no_warm:
+            print("[bench] warm start vs plain on held-out 48^3 phantoms ...", file=sys.stderr, flush=True)
+            ttr["c4_heldout"] = warm_vs_plain_heldout(dev)
+    P = data = c = None
     torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle sample ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, args.cpu_sample, c_true_np, data.cpu().numpy())
-    if not args.no_warm:
-        print("[bench] warm start vs plain ...", file=sys.stderr, flush=True)
-        ttr["warm_start"] = warm_vs_plain_heldout(dev)
-        if args.ttr_c5:
-            from paper_2504_16446_amd import warmstart
-            del P, data, c, c2
-            torch.cuda.empty_cache()
-            model = warmstart.load(warmstart.DEFAULT_WEIGHTS, dev)
-            ttr["warm_start_c5"] = warmstart.compare(model, synth.WORKLOADS["c5"], 1e-3, 1500)
+        cpu = cpu_baseline(w, n_sample, c_true_np, y_sel)
     print("[bench] precision report ...", file=sys.stderr, flush=True)
     precision = None if args.no_precision else precision_report(dev)
     print("[bench] derived quantities ...", file=sys.stderr, flush=True)
@@ -439,10 +480,13 @@ def main():
         "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n[0]}^3 voxels, ell_max {w.ell_max} ({w.n_coeff} coeffs), "
-                               f"{w.n_proj} projections, {w.nj}x{w.nk} px x {w.n_seg} segments; "
+                               f"{w.n_proj} projections, {w.nj}x{w.nk} px x {w.n_seg} segments, "
+                               f"{w.phantom} phantom, noise {w.noise}; "
                                f"step = one L-BFGS iteration (m=10, mu={w.mu})",
-                   "fwd_adj_algorithmic_bytes_per_step": 2 * per_dir},
+                   "fwd_adj_algorithmic_bytes_per_step": 2 * per_dir, "ray_samples_per_direction": samples,
+                   "forward_batch": forward_batch},
         "roofline": roofline,
+        "roofline_kernels": roofs,
         "cpu_baseline": cpu,
         "kernels": kernels,
         "time_to_residual": ttr,

@@ -25,8 +25,10 @@
  *      basis constants B[n_proj][n_seg][C] (float64, host).
  *    Coefficient index i(l, m) = l(l-1)/2 + l + m for even l, m = -l..l.
  *  - Pointers named *_dev are device pointers on the context's device; the
- *    caller allocates and owns them.  A context owns only its own tables and
- *    internal work buffers.
+ *    caller allocates and owns them, work buffers included (tt_set_workspace,
+ *    tt_lbfgs_create, tt_kappa, ...).  A context owns only its geometry tables
+ *    (ray frames and basis constants, allocated once by tt_create); no call
+ *    after tt_create allocates device memory.
  *  - Device work is enqueued on the context's stream (tt_set_stream) and is
  *    asynchronous unless stated otherwise.  A context must not be used from
  *    two host threads at once.
@@ -102,8 +104,9 @@ typedef struct tt_ctx tt_ctx;
 
 /* Build a context on the current HIP device: validates the geometry, computes
  * R_s = R_beta(beta_s) R_alpha(alpha_s), the ray frames and B_{sc,i} in
- * float64 on the host, uploads device tables and allocates work buffers.
- * Synchronous.  On failure *out is NULL. */
+ * float64 on the host and uploads them as device tables (the only device
+ * memory the library allocates).  Device computations need a workspace
+ * (tt_set_workspace) first.  Synchronous.  On failure *out is NULL. */
 int tt_create(const tt_geometry *geom, tt_ctx **out);  /* TT_EUNSUPPORTED for ell_max > 12 */
 /* Waits for the context's stream, then frees its tables and buffers. */
 void tt_destroy(tt_ctx *ctx);
@@ -133,9 +136,35 @@ int tt_set_projector(tt_ctx *ctx, int model);
 /* Number of real even-order SH coefficients up to ell_max (or TT_EINVAL). */
 int tt_num_coeffs(int ell_max);
 
-/* Sizes of this context: out6 = {nx*ny*nz*C, n_proj*nj*nk*n_seg, C,
- * unique segments, projections per forward batch, device work bytes}. */
-int tt_sizes(const tt_ctx *ctx, int64_t *out6);
+/* Sizes of this context: out8 = {nx*ny*nz*C, n_proj*nj*nk*n_seg, C,
+ * unique segments, projections per forward batch (0 before tt_set_workspace),
+ * attached workspace bytes, bytes of the context's own tables, bytes of one
+ * projection's mapped volume}. */
+int tt_sizes(const tt_ctx *ctx, int64_t *out8);
+
+/* Workspace of a context: float64 reduction partials, the antipodally folded
+ * adjoint input (n_proj nj nk U floats), a data-sized residual scratch and
+ * the coefficient-to-segment maps M_s = B_s c of one batch of projections
+ * ((nx+2)(ny+2)(nz+2) U floats each, zero border).  The forward evaluates
+ * Eq. forward_model batch by batch: a larger batch reads c fewer times.
+ * tt_workspace_bytes gives the bytes for a batch of forward_batch projections
+ * (rounded to what the map kernel accepts; forward_batch <= 1 gives the
+ * smallest valid workspace, >= n_proj the whole set in one batch).
+ * tt_set_workspace attaches caller memory (device, 256-byte aligned) and
+ * picks the largest batch that fits; TT_EINVAL below the smallest size.  The
+ * memory must stay allocated and untouched by the caller while attached; the
+ * zero border is written once, on the context's stream.  Calls that compute
+ * (tt_project, tt_adjoint, tt_loss_grad, the solver, tt_kappa,
+ * tt_voxel_preconditioner) return TT_EINVAL without a workspace. */
+int64_t tt_workspace_bytes(const tt_ctx *ctx, int forward_batch);
+int tt_set_workspace(tt_ctx *ctx, void *work_dev, size_t bytes);
+
+/* Host-only: *out = the number of ray samples (trilinear model) or plane cuts
+ * (Joseph's method) of all projections that touch the volume, i.e. the sample
+ * positions whose trilinear (bilinear) stencil meets at least one voxel.  Each
+ * touches up to 8 (4) voxels; the count sizes the arithmetic of the forward
+ * ray sums and of the adjoint's gather. */
+int tt_ray_samples(const tt_ctx *ctx, int64_t *out);
 
 /* Copy B_{sc,i} (Eq. projection_matrix) to the host: B[n_proj][n_seg][C]. */
 int tt_basis_matrix(const tt_ctx *ctx, double *B_host);
@@ -161,7 +190,8 @@ int tt_adjoint(tt_ctx *ctx, const float *y_dev, float *g_dev, float beta, const 
 /* Squared loss with L2 regularisation (Eqs. opt_prob_general_form, residual):
  *   r = A c - I_data,  L = sum w r^2 + mu sum c^2,  grad = 2 A^T (w r) + 2 mu c.
  * w_dev may be NULL (all ones).  loss_dev receives L as one float64 on the
- * device; resid_dev (data layout) may be NULL.  Overwrites grad_dev. */
+ * device; resid_dev (data layout) may be NULL (the residual then goes to the
+ * workspace's scratch).  Overwrites grad_dev. */
 int tt_loss_grad(tt_ctx *ctx, const float *c_dev, const float *data_dev, const float *w_dev,
                  double mu, double *loss_dev, float *grad_dev, float *resid_dev);
 
@@ -178,11 +208,19 @@ int tt_loss_grad(tt_ctx *ctx, const float *c_dev, const float *data_dev, const f
 /* ------------------------------------------------------------------------ */
 typedef struct tt_lbfgs tt_lbfgs;
 
-/* Allocate the solver state and its device history ((2m + 5) coefficient
- * vectors and two data vectors).  The data, weight and coefficient buffers
- * passed to tt_lbfgs_init must stay valid while the solver is used. */
-int tt_lbfgs_create(tt_ctx *ctx, int m, tt_lbfgs **out);
-/* Waits for the context's stream, then frees the solver (destroy it before its context). */
+/* Bytes of the solver workspace for history m (1..10): 2(m + 1) + 3
+ * coefficient-sized float vectors (s and y slots, two gradients, the
+ * direction), two data-sized float vectors (residual, A d), the float64 state
+ * and reduction partials, each 256-byte aligned. */
+int64_t tt_lbfgs_workspace_bytes(const tt_ctx *ctx, int m);
+/* Create a solver on the caller's workspace (device, 256-byte aligned, at
+ * least tt_lbfgs_workspace_bytes bytes; TT_EINVAL otherwise).  The history
+ * slots are cleared on the context's stream.  The workspace and the data,
+ * weight and coefficient buffers passed to tt_lbfgs_init must stay valid
+ * while the solver is used.  The context needs its own workspace too. */
+int tt_lbfgs_create(tt_ctx *ctx, int m, void *work_dev, size_t bytes, tt_lbfgs **out);
+/* Waits for the context's stream, then frees the host-side solver state
+ * (destroy it before its context; the workspace stays the caller's). */
 void tt_lbfgs_destroy(tt_lbfgs *st);
 
 /* Start from c_dev (read and updated in place): computes r, L and grad.
@@ -204,6 +242,12 @@ int tt_lbfgs_step_direction(tt_lbfgs *st, const float *d_dev);
 /* Synchronise and read the state: out4 = {loss, ||r||_2, ||I||_2,
  * accepted pairs}.  out4 may hold 4 doubles. */
 int tt_lbfgs_query(tt_lbfgs *st, double *out4);
+
+/* Recompute the residual from an explicit forward projection,
+ * r = A c - I_data, and with it the loss and ||r|| that tt_lbfgs_query
+ * reports (between iterations the solver updates r by r += alpha A d, which
+ * accumulates float32 rounding).  Asynchronous. */
+int tt_lbfgs_refresh(tt_lbfgs *st);
 
 /* Run up to max_iter iterations, stopping once ||r|| / ||I|| <= rel_tol
  * (checked before each iteration, one host sync per iteration).  hist (host,
@@ -250,32 +294,57 @@ int tt_adam(float *w, const float *g, float *m, float *v, int64_t n, int t, floa
  * [nvox][creal]; work holds >= 1024 doubles. */
 int tt_mse(const float *y, const float *t, int64_t nvox, int cpad, int creal, float scale, uint16_t *gy,
            double *loss, double *work, int64_t work_len, void *stream);
-/* out[v][c] = bf16(scale[c] (x[v][c] - shift[c])) for c < cin, 0 up to cpad
- * (shift, scale may be NULL). */
-int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, const float *shift, const float *scale,
-                 uint16_t *out, void *stream);
+/* out[v][c] = bf16(scale[c] (pre_scale x[v][c] - shift[c])) for c < cin, 0
+ * up to cpad (shift, scale may be NULL). */
+int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, float pre_scale, const float *shift,
+                 const float *scale, uint16_t *out, void *stream);
 
 /* Patchwise inference on T^3 tiles at per-axis origins ox[ntx], oy[nty],
  * oz[ntz] (device int arrays; tile t = (ix nty + iy) ntz + iz).  Origins must
  * satisfy o + T <= volume size, tiles covering the whole volume.
  * tt_tile_gather: tiles t0 .. t0+nt-1 of vol[X][Y][Z][cv] (channels < cin),
- * standardised and packed to bf16 out[nt][T][T][T][cpad].
+ * scaled by pre_scale, standardised and packed to bf16
+ * out[nt][T][T][T][cpad] as in tt_pack_bf16.
  * tt_tile_blend: out[X][Y][Z][cout] = sum_t w_t y_t / sum_t w_t on channels
  * < creal (0 above), y = all tiles' outputs [ntiles][T][T][T][cy] float,
  * w_t the product of per-axis linear ramps over `ramp` voxels on sides that
  * overlap a neighbouring tile. */
 int tt_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
-                   const int *oy, int nty, const int *oz, int ntz, int T, const float *shift, const float *scale,
-                   int t0, int nt, uint16_t *out, void *stream);
+                   const int *oy, int nty, const int *oz, int ntz, int T, float pre_scale, const float *shift,
+                   const float *scale, int t0, int nt, uint16_t *out, void *stream);
+
+/* Normalisation of the network input of the learned warm start (the paper's
+ * outlook on learned models, sect. 4): the backprojection A^T I is divided by
+ * kappa, the lower median (element (n-1)/2 of the n sorted values) over the
+ * voxels whose centre lies within `radius` of the volume centre of
+ * (A^T A u)_{v,0}, u the unit isotropic field (u_{v,0} = 1, other
+ * coefficients 0).  One forward and one adjoint on the context; the median is
+ * an exact radix selection on the float bit patterns.  work: device, 256-byte
+ * aligned, tt_normal_work_bytes bytes.  Synchronous; *kappa is a host double.
+ * TT_ENONFINITE if no voxel centre lies inside the ball. */
+int64_t tt_normal_work_bytes(const tt_ctx *ctx);
+int tt_kappa(tt_ctx *ctx, double radius, void *work_dev, size_t work_bytes, double *kappa);
+/* Per-channel standardisation statistics of y = pre_scale x over
+ * x[nvox][cstride] (channels c < nch <= 64): shift[c] = mean, scale[c] =
+ * 1 / max(unbiased standard deviation, 1e-12), as float.  Sums in float64
+ * with fixed-order partials (run-to-run identical).  work: device float64
+ * array of at least tt_channel_stats_work_len() elements.  Asynchronous. */
+int64_t tt_channel_stats_work_len(void);
+int tt_channel_stats(const float *x, int64_t nvox, int cstride, int nch, float pre_scale, float *shift, float *scale,
+                     double *work, int64_t work_len, void *stream);
 int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const int *ox, int ntx, const int *oy,
                   int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, void *stream);
 
+#define TT_REDUCE_WORK 4096
 /* ------------------------------------------------------------------------ */
 /* Other objectives on the same operator (sect. 3.5, "Optimization"):       */
 /* regularisers of the tensor field and fixed-step gradient descent with    */
 /* optional Nesterov momentum.  Coefficient arrays are device float         */
-/* [nx][ny][nz][C] (n = nx ny nz C elements); values accumulate in float64  */
-/* with one atomic add per block (summation order not fixed).               */
+/* [nx][ny][nz][C] (n = nx ny nz C elements).  Values accumulate in float64 */
+/* without atomics: each block writes a partial sum into `partials` (device */
+/* float64, at least TT_REDUCE_WORK elements, needed whenever a value is    */
+/* requested) and one pass adds them in a fixed order, so repeated calls    */
+/* give identical values.                                                   */
 /* ------------------------------------------------------------------------ */
 /* Laplacian regulariser lambda sum (Lap c)^2 with Lap the 7-point finite-
  * difference Laplacian of every coefficient channel, zero outside the volume:
@@ -284,19 +353,21 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
  * must not overlap.  TT_EUNSUPPORTED if C > 1024 or nx * ny * nz > 2^31 - 1
  * (z chunks of a row with their neighbours are staged in LDS). */
 int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambda, float *work, float *grad,
-                     double *value, void *stream);
+                     double *value, double *partials, int64_t partials_len, void *stream);
 /* Huber norm lambda sum h(c_e), h(x) = x^2 / (2 delta) for |x| <= delta and
  * |x| - delta / 2 otherwise (delta > 0): grad += lambda clamp(c / delta, -1, 1),
  * value[0] += lambda sum h if value is not NULL. */
-int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, void *stream);
+int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, double *partials,
+                 int64_t partials_len, void *stream);
 /* Huber loss of the residual (robust regression, the paper's HuberLoss):
  * r = I - data, y = w clamp(r / delta, -1, 1) (pass y to tt_adjoint for the
  * gradient A^T y), value[0] += sum w h(r) if value is not NULL.  I, data, y
  * have n floats (data-shaped); w may be NULL (all ones). */
 int tt_huber_loss(const float *I, const float *data, const float *w, int64_t n, double delta, float *y,
-                  double *value, void *stream);
+                  double *value, double *partials, int64_t partials_len, void *stream);
 /* value[0] += scale * sum x^2 over n floats (float64 accumulation). */
-int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *stream);
+int tt_sumsq(const float *x, int64_t n, double scale, double *value, double *partials, int64_t partials_len,
+             void *stream);
 /* One gradient step with momentum m on n floats, g = grad f(y):
  * c_new = y - step p g, y = c_new + m (c_new - c), c = c_new, with p an
  * optional diagonal preconditioner (n positive floats, NULL = 1; the paper's
@@ -305,6 +376,13 @@ int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *strea
  * m_k = (k-1)/(k+2).  c, y, g and p must be distinct buffers. */
 int tt_gd_step(float *c, float *y, const float *g, const float *precond, int64_t n, float step, float momentum,
                void *stream);
+/* Diagonal preconditioner for tt_gd_step (the MITRA-style weighting of the
+ * gradient, sect. 3.4): p[v][i] = 1 / max(d_v, floor_frac max_v d_v) for every
+ * coefficient i of voxel v, with d_v = (A^T A u)_{v,0} the normal operator's
+ * response to the unit isotropic field at voxel v.  p_dev has the coefficient
+ * layout; work as for tt_kappa (tt_normal_work_bytes).  Asynchronous on the
+ * context's stream. */
+int tt_voxel_preconditioner(tt_ctx *ctx, double floor_frac, float *p_dev, void *work_dev, size_t work_bytes);
 
 /* ------------------------------------------------------------------------ */
 /* Derived per-voxel quantities (the paper's section on deriving standard    */

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libtt_hip.so")
 TT_MAP_FP32, TT_MAP_BF16 = 0, 1
 TT_PROJ_TRILINEAR, TT_PROJ_JOSEPH = 0, 1
 TT_BASIS_SH, TT_BASIS_GK, TT_BASIS_NN = 0, 1, 2
+REDUCE_WORK = 4096  # TT_REDUCE_WORK: float64 partials of a value reduction
 KERNEL_CLASSES = ["map", "march", "fold", "backproject", "residual", "vector", "plan"]
 _ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EUNSUPPORTED"}
 
@@ -57,12 +58,22 @@ _SIGS = [
     ("tt_num_coeffs", C.c_int, [C.c_int]),
     ("tt_sizes", C.c_int, [_vp, C.POINTER(C.c_int64)]),
     ("tt_basis_matrix", C.c_int, [_vp, C.POINTER(C.c_double)]),
+    ("tt_ray_samples", C.c_int, [_vp, C.POINTER(C.c_int64)]),
     ("tt_geometry_basis", C.c_int, [C.POINTER(Geometry), C.POINTER(C.c_double)]),
     ("tt_sh_eval", C.c_int, [C.c_int, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("tt_project", C.c_int, [_vp, _fp, _fp]),
     ("tt_adjoint", C.c_int, [_vp, _fp, _fp, C.c_float, _fp]),
     ("tt_loss_grad", C.c_int, [_vp, _fp, _fp, _fp, C.c_double, _dp, _fp, _fp]),
-    ("tt_lbfgs_create", C.c_int, [_vp, C.c_int, C.POINTER(C.c_void_p)]),
+    ("tt_workspace_bytes", C.c_int64, [_vp, C.c_int]),
+    ("tt_set_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
+    ("tt_lbfgs_workspace_bytes", C.c_int64, [_vp, C.c_int]),
+    ("tt_lbfgs_create", C.c_int, [_vp, C.c_int, _vp, C.c_size_t, C.POINTER(C.c_void_p)]),
+    ("tt_lbfgs_refresh", C.c_int, [_vp]),
+    ("tt_normal_work_bytes", C.c_int64, [_vp]),
+    ("tt_kappa", C.c_int, [_vp, C.c_double, _vp, C.c_size_t, C.POINTER(C.c_double)]),
+    ("tt_voxel_preconditioner", C.c_int, [_vp, C.c_double, _fp, _vp, C.c_size_t]),
+    ("tt_channel_stats_work_len", C.c_int64, []),
+    ("tt_channel_stats", C.c_int, [_fp, C.c_int64, C.c_int, C.c_int, C.c_float, _fp, _fp, _dp, C.c_int64, _vp]),
     ("tt_lbfgs_destroy", None, [_vp]),
     ("tt_lbfgs_init", C.c_int, [_vp, _fp, _fp, _fp, C.c_double]),
     ("tt_lbfgs_step", C.c_int, [_vp]),
@@ -80,17 +91,18 @@ _SIGS = [
                                   _fp, _fp, _vp]),
     ("tt_adam", C.c_int, [_fp, _fp, _fp, _fp, C.c_int64, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     ("tt_mse", C.c_int, [_fp, _fp, C.c_int64, C.c_int, C.c_int, C.c_float, _vp, _dp, _dp, C.c_int64, _vp]),
-    ("tt_pack_bf16", C.c_int, [_fp, C.c_int64, C.c_int, C.c_int, _fp, _fp, _vp, _vp]),
+    ("tt_pack_bf16", C.c_int, [_fp, C.c_int64, C.c_int, C.c_int, C.c_float, _fp, _fp, _vp, _vp]),
     ("tt_tile_gather", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp,
-                                 C.c_int, _vp, C.c_int, C.c_int, _fp, _fp, C.c_int, C.c_int, _vp, _vp]),
+                                 C.c_int, _vp, C.c_int, C.c_int, C.c_float, _fp, _fp, C.c_int, C.c_int, _vp, _vp]),
     ("tt_tile_blend", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp,
                                 C.c_int, C.c_int, C.c_int, C.c_int, _fp, _vp]),
     ("tt_tensor_properties", C.c_int, [_fp, C.c_int64, C.c_int, _fp, _vp]),
-    ("tt_laplacian_reg", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _fp, _fp, _dp, _vp]),
-    ("tt_huber_reg", C.c_int, [_fp, C.c_int64, C.c_double, C.c_double, _fp, _dp, _vp]),
+    ("tt_laplacian_reg", C.c_int, [_fp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _fp, _fp, _dp, _dp,
+                                   C.c_int64, _vp]),
+    ("tt_huber_reg", C.c_int, [_fp, C.c_int64, C.c_double, C.c_double, _fp, _dp, _dp, C.c_int64, _vp]),
     ("tt_gd_step", C.c_int, [_fp, _fp, _fp, _fp, C.c_int64, C.c_float, C.c_float, _vp]),
-    ("tt_huber_loss", C.c_int, [_fp, _fp, _fp, C.c_int64, C.c_double, _fp, _dp, _vp]),
-    ("tt_sumsq", C.c_int, [_fp, C.c_int64, C.c_double, _dp, _vp]),
+    ("tt_huber_loss", C.c_int, [_fp, _fp, _fp, C.c_int64, C.c_double, _fp, _dp, _dp, C.c_int64, _vp]),
+    ("tt_sumsq", C.c_int, [_fp, C.c_int64, C.c_double, _dp, _dp, C.c_int64, _vp]),
     ("tt_last_error", C.c_char_p, []),
     ("tt_error_string", C.c_char_p, [C.c_int]),
 ]

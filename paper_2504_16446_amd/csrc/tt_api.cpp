@@ -45,14 +45,19 @@ struct tt_ctx {
     float *d_Bsw = nullptr;     // Bu in MFMA lane order (16-row tiles), for the forward map
     uint16_t *d_Bsw16 = nullptr; // bf16 Bu in MFMA lane order (16-row tiles, k blocks of 16), forward
     uint16_t *d_BuT16 = nullptr; // bf16 [S][Cp][16]: B^T with u padded to 16, adjoint
-    int pb = 1;                 // projections per forward batch
+    int pb = 0;                 // projections per forward batch (0: no workspace attached)
     long long vol_pad = 0;
-    float *d_M = nullptr;       // [pb][vol_pad][Up]
+    size_t per_proj = 0;        // bytes of one projection's mapped volume M
+    int n_part = 0;             // float64 reduction partials
+    // Caller-owned workspace (tt_set_workspace): partials, folded residual
+    // yf, a data-sized residual scratch and the mapped volumes of one batch.
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    double *d_part = nullptr;   // [n_part]
     float *d_yf = nullptr;      // [S][nj][nk][Up]
-    double *d_part = nullptr;   // reduction partials
-    int n_part = 0;
-    float *d_scratch = nullptr; // data-sized scratch for tt_loss_grad without resid
-    size_t work_bytes = 0;
+    float *d_resid = nullptr;   // [S][nj][nk][n_seg]
+    float *d_M = nullptr;       // [pb][vol_pad][Up], zero border
+    size_t table_bytes = 0;
     bool timing = false;
     struct Mark {
         int kind;
@@ -296,22 +301,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         for (int i = 0; i < d.Cp; ++i)
             for (int u = 0; u < d.Up; ++u) but16[((size_t)s * d.Cp + i) * 16 + u] = to_bf16(bu[((size_t)s * d.Up + u) * d.Cp + i]);
     c->vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
-    const size_t per_proj = (size_t)c->vol_pad * d.Up * sizeof(float);
-    // Projections per forward batch: the map reads c once per batch, so the
-    // batch should fill the map kernel's 256-row tiles (256 / Up projections)
-    // and be as large as memory allows; default budget 1/8 of the free device
-    // memory, clamped to [1, 24] GiB.
-    size_t free_b = 0, total_b = 0;
-    size_t budget = (size_t)1 << 30;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
-        budget = std::min<size_t>((size_t)24 << 30, std::max<size_t>((size_t)1 << 30, free_b / 8));
-    if (const char *e = std::getenv("TT_FORWARD_BATCH_BYTES")) budget = (size_t)std::strtoull(e, nullptr, 10);
-    c->pb = (int)std::max<size_t>(1, std::min<size_t>((size_t)S, budget / per_proj));
-    const int align = 16 / d.Up, full = 256 / d.Up;
-    if (c->pb < S) {
-        if (c->pb >= full) c->pb = c->pb / full * full;
-        else c->pb = std::max(align, c->pb / align * align);
-    }
+    c->per_proj = (size_t)c->vol_pad * d.Up * sizeof(float);
     // MFMA-ordered copy of Bu: tile rt, k-step ks, lane l -> Bu[16 rt + l % 16][4 ks + l / 16]
     std::vector<float> bsw(bu.size(), 0.0f);
     const int KS = d.Cp / 4;
@@ -320,7 +310,6 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
             for (int l = 0; l < 64; ++l)
                 bsw[((size_t)rt * KS + ks) * 64 + l] = bu[((size_t)rt * 16 + l % 16) * d.Cp + 4 * ks + l / 16];
     c->n_part = 1024 + std::max(4096, backproject_blocks(d));
-    const size_t yf_bytes = (size_t)S * d.nj * d.nk * d.Up * sizeof(float);
 
     auto cleanup = [&](int code, const std::string &msg) {
         tt_destroy(c);
@@ -330,17 +319,15 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         hipMalloc(&c->d_Bu, bu.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bsw, bsw.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bsw16, bsw16.size() * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&c->d_BuT16, but16.size() * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&c->d_M, per_proj * c->pb) != hipSuccess || hipMalloc(&c->d_yf, yf_bytes) != hipSuccess ||
-        hipMalloc(&c->d_part, sizeof(double) * c->n_part) != hipSuccess)
+        hipMalloc(&c->d_BuT16, but16.size() * sizeof(uint16_t)) != hipSuccess)
         return cleanup(TT_ENOMEM, "device allocation failed");
-    c->work_bytes = per_proj * c->pb + yf_bytes + sizeof(double) * c->n_part + bu.size() * 10 + but16.size() * 2;
+    c->table_bytes = sizeof(ProjFrame) * S + bu.size() * 10 + but16.size() * 2;
     if (hipMemcpy(c->d_frames, c->frames.data(), sizeof(ProjFrame) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bu, bu.data(), bu.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bsw, bsw.data(), bsw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bsw16, bsw16.data(), bsw16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_BuT16, but16.data(), but16.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->d_M, 0, per_proj * c->pb) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        hipDeviceSynchronize() != hipSuccess)
         return cleanup(TT_EHIP, "device upload failed");
     *out = c;
     return TT_OK;
@@ -356,10 +343,6 @@ void tt_destroy(tt_ctx *c)
     hipFree(c->d_Bsw);
     hipFree(c->d_Bsw16);
     hipFree(c->d_BuT16);
-    hipFree(c->d_M);
-    hipFree(c->d_yf);
-    hipFree(c->d_part);
-    hipFree(c->d_scratch);
     delete c;
 }
 
@@ -422,15 +405,140 @@ int tt_timing_read(tt_ctx *c, double *ms_total, int64_t *launches)
     return TT_OK;
 }
 
-int tt_sizes(const tt_ctx *c, int64_t *out6)
+int tt_sizes(const tt_ctx *c, int64_t *out8)
 {
-    if (!c || !out6) return fail(TT_EINVAL, "null pointer");
-    out6[0] = n_coef(c);
-    out6[1] = n_data(c);
-    out6[2] = c->d.C;
-    out6[3] = c->d.U;
-    out6[4] = c->pb;
-    out6[5] = (int64_t)c->work_bytes;
+    if (!c || !out8) return fail(TT_EINVAL, "null pointer");
+    out8[0] = n_coef(c);
+    out8[1] = n_data(c);
+    out8[2] = c->d.C;
+    out8[3] = c->d.U;
+    out8[4] = c->pb;
+    out8[5] = (int64_t)c->ws_bytes;
+    out8[6] = (int64_t)c->table_bytes;
+    out8[7] = (int64_t)c->per_proj;
+    return TT_OK;
+}
+
+// Workspace layout for a forward batch of pb projections (pb = 0: no mapped volumes).
+struct WsLayout {
+    size_t part, yf, resid, M, total;
+};
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static WsLayout ws_layout(const tt_ctx *c, int pb)
+{
+    WsLayout L;
+    size_t off = 0;
+    L.part = off;
+    off += align256(sizeof(double) * c->n_part);
+    L.yf = off;
+    off += align256(sizeof(float) * (size_t)c->d.S * c->d.nj * c->d.nk * c->d.Up);
+    L.resid = off;
+    off += align256(sizeof(float) * (size_t)n_data(c));
+    L.M = off;
+    off += align256(c->per_proj * (size_t)pb);
+    L.total = off;
+    return L;
+}
+// Largest valid forward batch not above pb: every batch but the last must
+// start on a 16-row map tile (pb a multiple of 16 / Up) and batches of 256 /
+// Up or more are kept whole multiples of the 256-row map block.  0 if none.
+static int batch_round_down(const tt_ctx *c, long long pb)
+{
+    const int S = c->d.S, align = 16 / c->d.Up, full = 256 / c->d.Up;
+    if (pb >= S) return S;
+    if (pb >= full) return (int)(pb / full * full);
+    return (int)(pb / align * align);
+}
+static int batch_min(const tt_ctx *c) { return std::min(c->d.S, 16 / c->d.Up); }
+
+static int need_ws(const tt_ctx *c)
+{
+    if (!c->ws) return fail(TT_EINVAL, "no workspace attached to the context (tt_set_workspace)");
+    return TT_OK;
+}
+
+int64_t tt_workspace_bytes(const tt_ctx *c, int forward_batch)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    int pb = batch_round_down(c, std::min(forward_batch, c->d.S));
+    pb = std::max(pb, batch_min(c));
+    return (int64_t)ws_layout(c, pb).total;
+}
+
+int tt_set_workspace(tt_ctx *c, void *work, size_t bytes)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    if (!work) return fail(TT_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(TT_EINVAL, "workspace must be 256-byte aligned");
+    const size_t base = ws_layout(c, 0).total;
+    const long long fit = bytes > base ? (long long)((bytes - base) / c->per_proj) : 0;
+    const int pb = batch_round_down(c, fit);
+    if (pb < batch_min(c))
+        return fail(TT_EINVAL, "workspace of " + std::to_string(bytes) + " bytes is below the minimum of " +
+                                   std::to_string(tt_workspace_bytes(c, 1)));
+    const WsLayout L = ws_layout(c, pb);
+    c->ws = static_cast<char *>(work);
+    c->ws_bytes = bytes;
+    c->pb = pb;
+    c->d_part = reinterpret_cast<double *>(c->ws + L.part);
+    c->d_yf = reinterpret_cast<float *>(c->ws + L.yf);
+    c->d_resid = reinterpret_cast<float *>(c->ws + L.resid);
+    c->d_M = reinterpret_cast<float *>(c->ws + L.M);
+    // the map writes only interior voxels: the border of every mapped volume stays zero
+    TT_HIP(hipMemsetAsync(c->d_M, 0, c->per_proj * (size_t)pb, c->stream));
+    return TT_OK;
+}
+
+// Number of ray samples (trilinear model) or plane cuts (Joseph) that touch the
+// volume: the ray parameter ranges the forward march visits, counted on the host
+// from the float64 ray frames with the same inequalities.
+int tt_ray_samples(const tt_ctx *c, int64_t *out)
+{
+    if (!c || !out) return fail(TT_EINVAL, "null pointer");
+    const Dims &d = c->d;
+    const double n3[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
+    long long total = 0;
+    for (int s = 0; s < d.S; ++s) {
+        const ProjFrame &f = c->frames[s];
+        for (int j = 0; j < d.nj; ++j)
+            for (int k = 0; k < d.nk; ++k) {
+                double b[3];
+                for (int a = 0; a < 3; ++a) b[a] = f.o[a] + j * f.ej[a] + k * f.ek[a] + 0.5 * (n3[a] + 1.0);
+                if (!d.joseph) {
+                    double tlo = -1e300, thi = 1e300;
+                    for (int a = 0; a < 3; ++a) {
+                        if (f.inv_d[a] != 0.0) {
+                            const double ia = f.inv_d[a] / (double)d.step;
+                            const double t1 = -b[a] * ia, t2 = (n3[a] + 1.0 - b[a]) * ia;
+                            tlo = std::max(tlo, std::min(t1, t2));
+                            thi = std::min(thi, std::max(t1, t2));
+                        } else if (!(b[a] > 0.0 && b[a] < n3[a] + 1.0)) {
+                            thi = -1e300;
+                        }
+                    }
+                    if (tlo < thi) total += std::max(0LL, (long long)std::floor(thi) - (long long)std::ceil(tlo) + 1);
+                } else {
+                    const int A = f.jos_a, B = (A + 1) % 3, Cc = (A + 2) % 3;
+                    double plo = 1.0, phi = n3[A];
+                    const int qq[2] = {B, Cc};
+                    for (int i = 0; i < 2; ++i) {
+                        const int q = qq[i];
+                        const double r = f.d[q] * f.inv_d[A];
+                        if (r != 0.0) {
+                            const double t1 = b[A] - b[q] / r, t2 = b[A] + (n3[q] + 1.0 - b[q]) / r;
+                            plo = std::max(plo, std::min(t1, t2));
+                            phi = std::min(phi, std::max(t1, t2));
+                        } else if (!(b[q] > 0.0 && b[q] < n3[q] + 1.0)) {
+                            phi = -1.0;
+                        }
+                    }
+                    const long long P0 = std::max(1LL, (long long)std::ceil(plo));
+                    const long long P1 = std::min((long long)n3[A], (long long)std::floor(phi));
+                    total += std::max(0LL, P1 - P0 + 1);
+                }
+            }
+    }
+    *out = total;
     return TT_OK;
 }
 
@@ -443,6 +551,7 @@ int tt_basis_matrix(const tt_ctx *c, double *B_host)
 
 static int project_impl(tt_ctx *c, const float *cin, float *I)
 {
+    if (int rc = need_ws(c)) return rc;
     for (int s0 = 0; s0 < c->d.S; s0 += c->pb) {
         const int np = std::min(c->pb, c->d.S - s0);
         hipError_t e;
@@ -470,6 +579,7 @@ int tt_project(tt_ctx *c, const float *cin, float *I)
 
 static int backproject_impl(tt_ctx *c, float *g, float beta, const float *cin, double *partials)
 {
+    if (int rc = need_ws(c)) return rc;
     hipError_t e;
     {
         KTimer t(c, TT_K_BACKPROJECT);
@@ -485,6 +595,7 @@ int tt_adjoint(tt_ctx *c, const float *y, float *g, float beta, const float *cin
 {
     if (!c || !y || !g) return fail(TT_EINVAL, "null pointer");
     if (beta != 0.0f && !cin) return fail(TT_EINVAL, "beta != 0 needs c");
+    if (int rc = need_ws(c)) return rc;
     {
         KTimer t(c, TT_K_FOLD);
         TT_HIP(launch_fold(c->d, y, c->d.step, c->d_yf, c->stream));
@@ -497,12 +608,8 @@ int tt_loss_grad(tt_ctx *c, const float *cin, const float *data, const float *w,
 {
     if (!c || !cin || !data || !loss || !grad) return fail(TT_EINVAL, "null pointer");
     if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(TT_EINVAL, "mu must be finite and >= 0");
-    float *r = resid;
-    if (!r) {
-        if (!c->d_scratch && hipMalloc(&c->d_scratch, sizeof(float) * n_data(c)) != hipSuccess)
-            return fail(TT_ENOMEM, "scratch allocation failed");
-        r = c->d_scratch;
-    }
+    if (int rc = need_ws(c)) return rc;
+    float *r = resid ? resid : c->d_resid;
     int rc = project_impl(c, cin, r);
     if (rc) return rc;
     const int nb = 1024;
@@ -519,52 +626,177 @@ int tt_loss_grad(tt_ctx *c, const float *cin, const float *data, const float *w,
 }
 
 // ---------------------------------------------------------------------------
+// Normal-operator diagonal of the isotropic field: d = (A^T A u)_{v,0}
+// ---------------------------------------------------------------------------
+struct NormalWork {
+    float *u, *I, *g;
+    char *red;
+    size_t total;
+};
+static NormalWork normal_layout(const tt_ctx *c, char *base)
+{
+    NormalWork L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    L.u = reinterpret_cast<float *>(take(sizeof(float) * n_coef(c)));
+    L.I = reinterpret_cast<float *>(take(sizeof(float) * n_data(c)));
+    L.g = reinterpret_cast<float *>(take(sizeof(float) * n_coef(c)));
+    L.red = take(std::max<size_t>(ball_median_work_bytes(), 1024 * sizeof(float)) + 256);
+    L.total = off;
+    return L;
+}
+
+int64_t tt_normal_work_bytes(const tt_ctx *c)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    return (int64_t)normal_layout(c, nullptr).total;
+}
+
+// g = A^T A u for the unit isotropic field u (g may alias nothing in the work area).
+static int normal_iso(tt_ctx *c, const NormalWork &L, float *g)
+{
+    const long long nvox = (long long)c->d.nx * c->d.ny * c->d.nz;
+    TT_HIP(launch_fill_iso(L.u, nvox, c->d.C, c->stream));
+    int rc = project_impl(c, L.u, L.I);
+    if (rc) return rc;
+    return tt_adjoint(c, L.I, g, 0.0f, nullptr);
+}
+
+static int check_work(const tt_ctx *c, void *work, size_t bytes)
+{
+    if (!work) return fail(TT_EINVAL, "work buffer is null");
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(TT_EINVAL, "work buffer must be 256-byte aligned");
+    if (bytes < normal_layout(c, nullptr).total) return fail(TT_EINVAL, "work buffer below tt_normal_work_bytes");
+    return TT_OK;
+}
+
+int tt_kappa(tt_ctx *c, double radius, void *work, size_t work_bytes, double *kappa)
+{
+    if (!c || !kappa) return fail(TT_EINVAL, "null pointer");
+    if (!(radius >= 0.0) || !std::isfinite(radius)) return fail(TT_EINVAL, "radius must be finite and >= 0");
+    if (int rc = check_work(c, work, work_bytes)) return rc;
+    const NormalWork L = normal_layout(c, static_cast<char *>(work));
+    int rc = normal_iso(c, L, L.g);
+    if (rc) return rc;
+    float *med = reinterpret_cast<float *>(L.red + ball_median_work_bytes());
+    TT_HIP(launch_ball_median(L.g, c->d.nx, c->d.ny, c->d.nz, c->d.C, 0, radius, L.red, med, c->stream));
+    float h = 0.0f;
+    TT_HIP(hipMemcpyAsync(&h, med, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    TT_HIP(hipStreamSynchronize(c->stream));
+    if (!std::isfinite(h)) return fail(TT_ENONFINITE, "no voxel centre inside the support ball");
+    *kappa = h;
+    return TT_OK;
+}
+
+int tt_voxel_preconditioner(tt_ctx *c, double floor_frac, float *p, void *work, size_t work_bytes)
+{
+    if (!c || !p) return fail(TT_EINVAL, "null pointer");
+    if (!(floor_frac > 0.0) || !std::isfinite(floor_frac)) return fail(TT_EINVAL, "floor_frac must be > 0");
+    if (int rc = check_work(c, work, work_bytes)) return rc;
+    const NormalWork L = normal_layout(c, static_cast<char *>(work));
+    int rc = normal_iso(c, L, p);
+    if (rc) return rc;
+    TT_HIP(launch_voxel_precond(p, (long long)c->d.nx * c->d.ny * c->d.nz, c->d.C, (float)floor_frac,
+                                reinterpret_cast<float *>(L.red), c->stream));
+    return TT_OK;
+}
+
+int64_t tt_channel_stats_work_len(void) { return (int64_t)chstats_work_doubles(); }
+
+int tt_channel_stats(const float *x, int64_t nvox, int cstride, int nch, float pre_scale, float *shift, float *scale,
+                     double *work, int64_t work_len, void *stream)
+{
+    if (!x || !shift || !scale || !work) return fail(TT_EINVAL, "null pointer");
+    if (nvox < 1 || nch < 1 || nch > 64 || cstride < nch) return fail(TT_ESHAPE, "need nvox >= 1, 1 <= nch <= 64 and cstride >= nch");
+    if (!std::isfinite(pre_scale)) return fail(TT_EINVAL, "pre_scale must be finite");
+    if (work_len < (int64_t)chstats_work_doubles()) return fail(TT_EINVAL, "work below tt_channel_stats_work_len()");
+    TT_HIP(launch_channel_stats(x, nvox, cstride, nch, pre_scale, shift, scale, work, (hipStream_t)stream));
+    return TT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // L-BFGS
 // ---------------------------------------------------------------------------
 void tt_lbfgs_destroy(tt_lbfgs *st)
 {
     if (!st) return;
-    if (st->ctx) hipStreamSynchronize(st->ctx->stream);
-    for (float *p : st->s) hipFree(p);
-    for (float *p : st->y) hipFree(p);
-    hipFree(st->g[0]);
-    hipFree(st->g[1]);
-    hipFree(st->d);
-    hipFree(st->r);
-    hipFree(st->q);
-    hipFree(st->st);
-    hipFree(st->ist);
-    hipFree(st->part);
+    if (st->ctx) hipStreamSynchronize(st->ctx->stream);  // queued kernels may still use the workspace
     delete st;
 }
 
-int tt_lbfgs_create(tt_ctx *c, int m, tt_lbfgs **out)
+// Solver workspace: m + 1 slots each for s and y, two gradients and the
+// direction (coefficient-sized), residual and A d (data-sized), the float64 /
+// int state and the reduction partials, each 256-byte aligned.
+static size_t lbfgs_layout(const tt_ctx *c, int m, tt_lbfgs *st, char *base)
+{
+    const size_t vb = align256(sizeof(float) * n_coef(c)), db = align256(sizeof(float) * n_data(c));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    for (int i = 0; i <= m; ++i) {
+        char *ps = take(vb), *py = take(vb);
+        if (st) {
+            st->s[i] = reinterpret_cast<float *>(ps);
+            st->y[i] = reinterpret_cast<float *>(py);
+        }
+    }
+    char *g0 = take(vb), *g1 = take(vb), *d = take(vb), *r = take(db), *q = take(db);
+    char *sd = take(sizeof(double) * kStateDoubles), *si = take(sizeof(int) * kStateInts);
+    char *part = take(sizeof(double) * (kMaxBasis + 1) * lbfgs_blocks());
+    if (st) {
+        st->g[0] = reinterpret_cast<float *>(g0);
+        st->g[1] = reinterpret_cast<float *>(g1);
+        st->d = reinterpret_cast<float *>(d);
+        st->r = reinterpret_cast<float *>(r);
+        st->q = reinterpret_cast<float *>(q);
+        st->st = reinterpret_cast<double *>(sd);
+        st->ist = reinterpret_cast<int *>(si);
+        st->part = reinterpret_cast<double *>(part);
+    }
+    return off;
+}
+
+int64_t tt_lbfgs_workspace_bytes(const tt_ctx *c, int m)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    if (m < 1 || m > kMaxM) return fail(TT_EUNSUPPORTED, "history m must be 1.." + std::to_string(kMaxM));
+    return (int64_t)lbfgs_layout(c, m, nullptr, nullptr);
+}
+
+int tt_lbfgs_create(tt_ctx *c, int m, void *work, size_t bytes, tt_lbfgs **out)
 {
     if (!out) return fail(TT_EINVAL, "out is null");
     *out = nullptr;
     if (!c) return fail(TT_EINVAL, "ctx is null");
     if (m < 1 || m > kMaxM) return fail(TT_EUNSUPPORTED, "history m must be 1.." + std::to_string(kMaxM));
+    if (!work) return fail(TT_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(TT_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = lbfgs_layout(c, m, nullptr, nullptr);
+    if (bytes < need)
+        return fail(TT_EINVAL, "L-BFGS workspace of " + std::to_string(bytes) + " bytes is below the " +
+                                   std::to_string(need) + " needed");
     tt_lbfgs *st = new (std::nothrow) tt_lbfgs();
     if (!st) return fail(TT_ENOMEM, "host allocation failed");
     st->ctx = c;
     st->m = m;
-    const size_t vb = sizeof(float) * n_coef(c), db = sizeof(float) * n_data(c);
     st->s.assign(m + 1, nullptr);
     st->y.assign(m + 1, nullptr);
-    bool ok = true;
+    lbfgs_layout(c, m, st, static_cast<char *>(work));
+    // history slots start at zero (masked out until filled, but never read uninitialised)
+    const size_t vb = sizeof(float) * n_coef(c);
     for (int i = 0; i <= m; ++i) {
-        ok &= hipMalloc(&st->s[i], vb) == hipSuccess && hipMemset(st->s[i], 0, vb) == hipSuccess;
-        ok &= hipMalloc(&st->y[i], vb) == hipSuccess && hipMemset(st->y[i], 0, vb) == hipSuccess;
-    }
-    ok &= hipMalloc(&st->g[0], vb) == hipSuccess && hipMalloc(&st->g[1], vb) == hipSuccess;
-    ok &= hipMalloc(&st->d, vb) == hipSuccess;
-    ok &= hipMalloc(&st->r, db) == hipSuccess && hipMalloc(&st->q, db) == hipSuccess;
-    ok &= hipMalloc(&st->st, sizeof(double) * kStateDoubles) == hipSuccess;
-    ok &= hipMalloc(&st->ist, sizeof(int) * kStateInts) == hipSuccess;
-    ok &= hipMalloc(&st->part, sizeof(double) * (kMaxBasis + 1) * lbfgs_blocks()) == hipSuccess;
-    if (!ok || hipDeviceSynchronize() != hipSuccess) {
-        tt_lbfgs_destroy(st);
-        return fail(TT_ENOMEM, "L-BFGS device allocation failed");
+        if (hipMemsetAsync(st->s[i], 0, vb, c->stream) != hipSuccess ||
+            hipMemsetAsync(st->y[i], 0, vb, c->stream) != hipSuccess) {
+            delete st;
+            return fail(TT_EHIP, "clearing the L-BFGS history failed");
+        }
     }
     *out = st;
     return TT_OK;
@@ -704,6 +936,23 @@ int tt_lbfgs_query(tt_lbfgs *st, double *out4)
     return TT_OK;
 }
 
+int tt_lbfgs_refresh(tt_lbfgs *st)
+{
+    if (!st || !st->inited) return fail(TT_EINVAL, "solver not initialised");
+    tt_ctx *c = st->ctx;
+    hipStream_t s = c->stream;
+    int rc = project_impl(c, st->c, st->r);
+    if (rc) return rc;
+    {
+        KTimer t(c, TT_K_RESIDUAL);
+        TT_HIP(launch_residual_fold(c->d, st->r, st->data, st->w, st->r, c->d_yf, c->d_part, 1024, s));
+        TT_HIP(launch_sum_partials(c->d_part, 1024, st->st + kLossR, 1.0, 0, s));
+    }
+    KTimer t(c, TT_K_VECTOR);
+    TT_HIP(lbfgs_wnorm2(st->r, nullptr, n_data(c), st->part, st->st + kRR, s));
+    return TT_OK;
+}
+
 int tt_lbfgs_run(tt_lbfgs *st, int max_iter, double rel_tol, double *hist, int *iters_out)
 {
     if (!st) return fail(TT_EINVAL, "null pointer");
@@ -793,27 +1042,29 @@ int tt_mse(const float *y, const float *t, int64_t nvox, int cpad, int creal, fl
     return TT_OK;
 }
 
-int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, const float *shift, const float *scale,
-                 uint16_t *out, void *stream)
+int tt_pack_bf16(const float *x, int64_t nvox, int cin, int cpad, float pre_scale, const float *shift,
+                 const float *scale, uint16_t *out, void *stream)
 {
     if (!x || !out) return fail(TT_EINVAL, "null pointer");
     if (nvox < 0 || cin < 1 || cpad < cin) return fail(TT_ESHAPE, "bad sizes");
+    if (!std::isfinite(pre_scale)) return fail(TT_EINVAL, "pre_scale must be finite");
     if (nvox == 0) return TT_OK;
-    TT_HIP(net_pack(x, nvox, cin, cpad, shift, scale, out, (hipStream_t)stream));
+    TT_HIP(net_pack(x, nvox, cin, cpad, pre_scale, shift, scale, out, (hipStream_t)stream));
     return TT_OK;
 }
 
 int tt_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
-                   const int *oy, int nty, const int *oz, int ntz, int T, const float *shift, const float *scale,
-                   int t0, int nt, uint16_t *out, void *stream)
+                   const int *oy, int nty, const int *oz, int ntz, int T, float pre_scale, const float *shift,
+                   const float *scale, int t0, int nt, uint16_t *out, void *stream)
 {
     if (!vol || !ox || !oy || !oz || !out) return fail(TT_EINVAL, "null pointer");
     if (X < 1 || Y < 1 || Z < 1 || cin < 1 || cv < cin || cpad < cin || T < 1 || ntx < 1 || nty < 1 || ntz < 1)
         return fail(TT_ESHAPE, "bad sizes");
     if (t0 < 0 || nt < 0 || t0 + nt > ntx * nty * ntz) return fail(TT_EINVAL, "tile range out of bounds");
+    if (!std::isfinite(pre_scale)) return fail(TT_EINVAL, "pre_scale must be finite");
     if (nt == 0) return TT_OK;
-    TT_HIP(net_tile_gather(vol, X, Y, Z, cv, cin, cpad, ox, ntx, oy, nty, oz, ntz, T, shift, scale, t0, nt, out,
-                           (hipStream_t)stream));
+    TT_HIP(net_tile_gather(vol, X, Y, Z, cv, cin, cpad, ox, ntx, oy, nty, oz, ntz, T, pre_scale, shift, scale, t0, nt,
+                           out, (hipStream_t)stream));
     return TT_OK;
 }
 
@@ -828,46 +1079,63 @@ int tt_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const 
     return TT_OK;
 }
 
-int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambda, float *work, float *grad,
-                     double *value, void *stream)
+static int check_partials(const double *partials, int64_t len)
 {
+    if (!partials) return fail(TT_EINVAL, "partials is null (a value needs TT_REDUCE_WORK doubles)");
+    if (len < kReduceBlocks) return fail(TT_EINVAL, "partials must hold TT_REDUCE_WORK doubles");
+    return TT_OK;
+}
+
+int tt_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lambda, float *work, float *grad,
+                     double *value, double *partials, int64_t partials_len, void *stream)
+{
+    static_assert(TT_REDUCE_WORK == kReduceBlocks, "partials length");
     if (!c || !work || !grad) return fail(TT_EINVAL, "null pointer");
+    if (value)
+        if (int rc = check_partials(partials, partials_len)) return rc;
     if (nx < 1 || ny < 1 || nz < 1 || C < 1) return fail(TT_ESHAPE, "sizes must be >= 1");
     if (C > kLapMaxC || (long long)nx * ny * nz > 0x7fffffffLL)
         return fail(TT_EUNSUPPORTED, "C above " + std::to_string(kLapMaxC) + " or nx * ny * nz above 2^31");
     if (!std::isfinite(lambda)) return fail(TT_EINVAL, "lambda must be finite");
-    TT_HIP(launch_laplacian_reg(c, nx, ny, nz, C, lambda, work, grad, value, (hipStream_t)stream));
+    TT_HIP(launch_laplacian_reg(c, nx, ny, nz, C, lambda, work, grad, value, partials, (hipStream_t)stream));
     return TT_OK;
 }
 
-int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, void *stream)
+int tt_huber_reg(const float *c, int64_t n, double delta, double lambda, float *grad, double *value, double *partials,
+                 int64_t partials_len, void *stream)
 {
     if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
+    if (value)
+        if (int rc = check_partials(partials, partials_len)) return rc;
     if (!(delta > 0.0) || !std::isfinite(delta) || !std::isfinite(lambda)) return fail(TT_EINVAL, "bad delta or lambda");
     if (n == 0) return TT_OK;
     if (!c || !grad) return fail(TT_EINVAL, "null pointer");
-    TT_HIP(launch_huber_reg(c, n, delta, lambda, grad, value, (hipStream_t)stream));
+    TT_HIP(launch_huber_reg(c, n, delta, lambda, grad, value, partials, (hipStream_t)stream));
     return TT_OK;
 }
 
 int tt_huber_loss(const float *I, const float *data, const float *w, int64_t n, double delta, float *y,
-                  double *value, void *stream)
+                  double *value, double *partials, int64_t partials_len, void *stream)
 {
     if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
+    if (value)
+        if (int rc = check_partials(partials, partials_len)) return rc;
     if (!(delta > 0.0) || !std::isfinite(delta)) return fail(TT_EINVAL, "delta must be > 0");
     if (n == 0) return TT_OK;
     if (!I || !data || !y) return fail(TT_EINVAL, "null pointer");
-    TT_HIP(launch_huber_loss(I, data, w, n, delta, y, value, (hipStream_t)stream));
+    TT_HIP(launch_huber_loss(I, data, w, n, delta, y, value, partials, (hipStream_t)stream));
     return TT_OK;
 }
 
-int tt_sumsq(const float *x, int64_t n, double scale, double *value, void *stream)
+int tt_sumsq(const float *x, int64_t n, double scale, double *value, double *partials, int64_t partials_len,
+             void *stream)
 {
     if (n < 0) return fail(TT_ESHAPE, "n must be >= 0");
     if (!value) return fail(TT_EINVAL, "null value");
+    if (int rc = check_partials(partials, partials_len)) return rc;
     if (n == 0) return TT_OK;
     if (!x) return fail(TT_EINVAL, "null pointer");
-    TT_HIP(launch_sumsq(x, n, scale, value, (hipStream_t)stream));
+    TT_HIP(launch_sumsq(x, n, scale, value, partials, (hipStream_t)stream));
     return TT_OK;
 }
 

@@ -117,15 +117,36 @@ hipError_t launch_tensor_props(const float *c, long long nvox, int C, float *out
 
 // Regularisers and the gradient-descent update (tt_reg.hip).
 constexpr int kLapMaxC = 1024;  // coefficients per voxel supported by the Laplacian
+// Value reductions write one float64 partial per block (at most kReduceBlocks)
+// into `partials` and add them in block order: value[0] += scale * sum.
+constexpr int kReduceBlocks = 4096;
 hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lam, float *work, float *grad,
-                                double *value, hipStream_t st);
+                                double *value, double *partials, hipStream_t st);
 hipError_t launch_huber_reg(const float *c, long long n, double delta, double lam, float *grad, double *value,
-                            hipStream_t st);
+                            double *partials, hipStream_t st);
 hipError_t launch_huber_loss(const float *I, const float *data, const float *w, long long n, double delta, float *y,
-                             double *value, hipStream_t st);
-hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, hipStream_t st);
+                             double *value, double *partials, hipStream_t st);
+hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, double *partials, hipStream_t st);
 hipError_t launch_nesterov(float *c, float *y, const float *g, const float *p, long long n, float step, float m,
                            hipStream_t st);
+
+// Normal-operator diagonal and input statistics (tt_stats.hip).
+// u[v][i] = (i == 0) for nvox voxels of C coefficients.
+hipError_t launch_fill_iso(float *u, long long nvox, int C, hipStream_t st);
+// out[0] = lower median of g[v][ch] over the voxels v whose centre lies within
+// `radius` of the volume centre (NaN if there are none); work holds
+// ball_median_work_bytes() bytes.
+size_t ball_median_work_bytes();
+hipError_t launch_ball_median(const float *g, int nx, int ny, int nz, int C, int ch, double radius, void *work,
+                              float *out, hipStream_t st);
+// In place: p[v][i] = 1 / max(p[v][0], floor_frac * max_v p[v][0]) for all i;
+// partial holds 1024 floats.
+hipError_t launch_voxel_precond(float *p, long long nvox, int C, float floor_frac, float *partial, hipStream_t st);
+// shift[c] = mean of pre x[v][c], scale[c] = 1 / (unbiased standard deviation,
+// floored at 1e-12), c < nch <= 64; work holds chstats_work_doubles() doubles.
+size_t chstats_work_doubles();
+hipError_t launch_channel_stats(const float *x, long long nvox, int cstride, int nch, float pre, float *shift,
+                                float *scale, double *work, hipStream_t st);
 
 // Reductions: out[slot] = scale * sum of partials[0..n).
 hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,
@@ -144,10 +165,10 @@ hipError_t net_adam(float *w, const float *g, float *m, float *v, long long n, i
                     float eps, hipStream_t st);
 hipError_t net_mse(const float *y, const float *t, long long nvox, int cpad, int creal, float scale, uint16_t *gy,
                    double *partials, int nblocks, double *loss, hipStream_t st);
-hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, const float *shift, const float *scale,
-                    uint16_t *out, hipStream_t st);
+hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, float pre, const float *shift,
+                    const float *scale, uint16_t *out, hipStream_t st);
 hipError_t net_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
-                           const int *oy, int nty, const int *oz, int ntz, int T, const float *shift,
+                           const int *oy, int nty, const int *oz, int ntz, int T, float pre, const float *shift,
                            const float *scale, int t0, int nt, uint16_t *out, hipStream_t st);
 hipError_t net_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z, const int *ox, int ntx, const int *oy,
                           int nty, const int *oz, int ntz, int T, int ramp, int cout, float *out, hipStream_t st);

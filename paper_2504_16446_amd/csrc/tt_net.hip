@@ -338,8 +338,8 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const 
 
 // out[v][c] = bf16(scale[c] * (x[v][c] - shift[c])) for c < cin, 0 for cin <= c < cpad
 __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, long long nvox, int cin, int cpad,
-                                              const float *__restrict__ shift, const float *__restrict__ scale,
-                                              u16 *__restrict__ out)
+                                              float pre, const float *__restrict__ shift,
+                                              const float *__restrict__ scale, u16 *__restrict__ out)
 {
     const long long n = nvox * cpad;
     for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, long 
         const int c = (int)(e % cpad);
         float val = 0.0f;
         if (c < cin) {
-            val = x[v * cin + c];
+            val = pre * x[v * cin + c];
             if (shift) val -= shift[c];
             if (scale) val *= scale[c];
         }
@@ -357,11 +357,11 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ x, long 
 
 // Patchwise inference.  Tiles of T^3 voxels at per-axis origins ox[], oy[], oz[]
 // (tile t = (i nx_t + j) ny_t... in x-major order).
-// gather: out[t][T^3][cpad] = bf16(scale[c] (vol[o_t + u][c] - shift[c])) for c < cin.
+// gather: out[t][T^3][cpad] = bf16(scale[c] (pre vol[o_t + u][c] - shift[c])) for c < cin.
 __global__ __launch_bounds__(256) void k_tile_gather(const float *__restrict__ vol, int X, int Y, int Z, int cv, int cin,
                                                      int cpad, const int *__restrict__ ox, int ntx,
                                                      const int *__restrict__ oy, int nty, const int *__restrict__ oz,
-                                                     int ntz, int T, const float *__restrict__ shift,
+                                                     int ntz, int T, float pre, const float *__restrict__ shift,
                                                      const float *__restrict__ scale, int t0, int nt,
                                                      u16 *__restrict__ out)
 {
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256) void k_tile_gather(const float *__restrict__ v
         const int gx = ox[ix] + ux, gy = oy[iy] + uy, gz = oz[iz] + uz;
         float v = 0.0f;
         if (c < cin && gx < X && gy < Y && gz < Z) {
-            v = vol[(((long long)gx * Y + gy) * Z + gz) * cv + c];
+            v = pre * vol[(((long long)gx * Y + gy) * Z + gz) * cv + c];
             if (shift) v -= shift[c];
             if (scale) v *= scale[c];
         }
@@ -535,12 +535,12 @@ hipError_t net_mse(const float *y, const float *t, long long nvox, int cpad, int
 }
 
 hipError_t net_tile_gather(const float *vol, int X, int Y, int Z, int cv, int cin, int cpad, const int *ox, int ntx,
-                           const int *oy, int nty, const int *oz, int ntz, int T, const float *shift,
+                           const int *oy, int nty, const int *oz, int ntz, int T, float pre, const float *shift,
                            const float *scale, int t0, int nt, uint16_t *out, hipStream_t st)
 {
     const long long n = (long long)T * T * T * cpad * nt;
     hipLaunchKernelGGL(k_tile_gather, dim3(grid_for(n)), dim3(256), 0, st, vol, X, Y, Z, cv, cin, cpad, ox, ntx, oy, nty,
-                       oz, ntz, T, shift, scale, t0, nt, out);
+                       oz, ntz, T, pre, shift, scale, t0, nt, out);
     return hipGetLastError();
 }
 
@@ -553,10 +553,11 @@ hipError_t net_tile_blend(const float *y, int cy, int creal, int X, int Y, int Z
     return hipGetLastError();
 }
 
-hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, const float *shift, const float *scale,
-                    uint16_t *out, hipStream_t st)
+hipError_t net_pack(const float *x, long long nvox, int cin, int cpad, float pre, const float *shift,
+                    const float *scale, uint16_t *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(nvox * cpad)), dim3(256), 0, st, x, nvox, cin, cpad, shift, scale, out);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(nvox * cpad)), dim3(256), 0, st, x, nvox, cin, cpad, pre, shift, scale,
+                       out);
     return hipGetLastError();
 }
 

@@ -1,7 +1,9 @@
 // Other objectives on the same operator (the paper's sect. 3.5, "Optimization"):
 // the finite-difference Laplacian and Huber-norm regularisers of the tensor
 // field and the fixed-step gradient-descent update with Nesterov momentum.
-// All are HBM streams over coefficient-sized arrays.
+// All are HBM streams over coefficient-sized arrays.  Objective values are
+// reduced without atomics: every block writes one float64 partial sum and a
+// single-block pass adds them in block order, so values repeat bit for bit.
 #include "tt_device.h"
 #include "tt_internal.h"
 
@@ -22,77 +24,87 @@ typedef float f4r __attribute__((ext_vector_type(4)));
 
 template <bool ACC>
 __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ in, int nx, int ny, int nz, int C,
-                                                   int zc, float *__restrict__ out, float scale, double lam,
-                                                   double *__restrict__ value, int aligned)
+                                                   int zc, float *__restrict__ out, float scale,
+                                                   double *__restrict__ partials, int aligned)
 {
     __shared__ double ws[4];
     extern __shared__ float rowc[];  // (zc + 2) C floats: voxels z0 - 1 .. z0 + zc
     const int nzc = (nz + zc - 1) / zc;
-    const int chunk = blockIdx.x % nzc, rowi = blockIdx.x / nzc;
-    const int x = rowi / ny, y = rowi % ny;
-    const int z0 = chunk * zc, z1 = min(nz, z0 + zc);
-    const int len = (z1 - z0) * C;  // output floats of this block
-    const long long rowlen = (long long)nz * C;
-    const long long base = ((long long)x * ny + y) * rowlen + (long long)z0 * C;
-    const float *r0 = in + base;
-    const long long sx = (long long)ny * rowlen;
-    const float *nb[4] = {x > 0 ? r0 - sx : nullptr, x + 1 < nx ? r0 + sx : nullptr, y > 0 ? r0 - rowlen : nullptr,
-                          y + 1 < ny ? r0 + rowlen : nullptr};
-    // rowc[C + e] = r0[e] for e in [-C, len + C), zero beyond the volume
-    const int lo = z0 > 0 ? -C : 0, hi = z1 < nz ? len + C : len;
-    for (int e = threadIdx.x - C; e < len + C; e += 256) rowc[C + e] = (e >= lo && e < hi) ? r0[e] : 0.0f;
-    __syncthreads();
-    // z0 C is a multiple of 4 (zc is), so with 4 | nz C every chunk starts 16-byte aligned
-    const bool vec = aligned && (rowlen & 3) == 0;
-    const int n4 = vec ? len / 4 : 0;
+    const long long nchunks = (long long)nx * ny * nzc;
     double ss = 0.0;
-    for (int e4 = threadIdx.x; e4 < n4; e4 += 256) {
-        f4r acc;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) acc[l] = rowc[C + 4 * e4 + l - C] + rowc[C + 4 * e4 + l + C] - 6.0f * rowc[C + 4 * e4 + l];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (nb[q]) acc += reinterpret_cast<const f4r *>(nb[q])[e4];
-        f4r *o = reinterpret_cast<f4r *>(out + base) + e4;
-        if (ACC) {
-            *o = scale * acc + *o;
-        } else {
-            *o = acc;
-#pragma unroll
-            for (int l = 0; l < 4; ++l) ss += (double)acc[l] * (double)acc[l];
+    for (long long bi = blockIdx.x; bi < nchunks; bi += gridDim.x) {
+        __syncthreads();  // the previous chunk's LDS reads are done
+        const int chunk = (int)(bi % nzc);
+        const long long rowi = bi / nzc;
+        const int x = (int)(rowi / ny), y = (int)(rowi % ny);
+        const int z0 = chunk * zc, z1 = min(nz, z0 + zc);
+        const int len = (z1 - z0) * C;  // output floats of this block
+        const long long rowlen = (long long)nz * C;
+        const long long base = ((long long)x * ny + y) * rowlen + (long long)z0 * C;
+        const float *r0 = in + base;
+        const long long sx = (long long)ny * rowlen;
+        const float *nb[4] = {x > 0 ? r0 - sx : nullptr, x + 1 < nx ? r0 + sx : nullptr, y > 0 ? r0 - rowlen : nullptr,
+                              y + 1 < ny ? r0 + rowlen : nullptr};
+        // rowc[C + e] = r0[e] for e in [-C, len + C), zero beyond the volume
+        const int lo = z0 > 0 ? -C : 0, hi = z1 < nz ? len + C : len;
+        for (int e = threadIdx.x - C; e < len + C; e += 256) rowc[C + e] = (e >= lo && e < hi) ? r0[e] : 0.0f;
+        __syncthreads();
+        // z0 C is a multiple of 4 (zc is), so with 4 | nz C every chunk starts 16-byte aligned
+        const bool vec = aligned && (rowlen & 3) == 0;
+        const int n4 = vec ? len / 4 : 0;
+        for (int e4 = threadIdx.x; e4 < n4; e4 += 256) {
+            f4r acc;
+    #pragma unroll
+            for (int l = 0; l < 4; ++l) acc[l] = rowc[C + 4 * e4 + l - C] + rowc[C + 4 * e4 + l + C] - 6.0f * rowc[C + 4 * e4 + l];
+    #pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (nb[q]) acc += reinterpret_cast<const f4r *>(nb[q])[e4];
+            f4r *o = reinterpret_cast<f4r *>(out + base) + e4;
+            if (ACC) {
+                *o = scale * acc + *o;
+            } else {
+                *o = acc;
+    #pragma unroll
+                for (int l = 0; l < 4; ++l) ss += (double)acc[l] * (double)acc[l];
+            }
+        }
+        for (int e = 4 * n4 + threadIdx.x; e < len; e += 256) {
+            float acc = rowc[e] + rowc[e + 2 * C] - 6.0f * rowc[C + e];
+    #pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (nb[q]) acc += nb[q][e];
+            if (ACC) {
+                out[base + e] = fmaf(scale, acc, out[base + e]);
+            } else {
+                out[base + e] = acc;
+                ss += (double)acc * (double)acc;
+            }
         }
     }
-    for (int e = 4 * n4 + threadIdx.x; e < len; e += 256) {
-        float acc = rowc[e] + rowc[e + 2 * C] - 6.0f * rowc[C + e];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (nb[q]) acc += nb[q][e];
-        if (ACC) {
-            out[base + e] = fmaf(scale, acc, out[base + e]);
-        } else {
-            out[base + e] = acc;
-            ss += (double)acc * (double)acc;
-        }
-    }
-    if (!ACC && value) {
+    if (!ACC && partials) {
         const double t = block_sum(ss, ws);
-        if (threadIdx.x == 0) atomicAdd(value, lam * t);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
     }
 }
 
 hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lam, float *work, float *grad,
-                                double *value, hipStream_t st)
+                                double *value, double *partials, hipStream_t st)
 {
     const int zc = std::max(4, (kLapChunkFloats / C) & ~3);  // multiple of 4
-    const long long blocks = (long long)nx * ny * ((nz + zc - 1) / zc);
-    if (blocks > 0x7fffffffLL || C > kLapMaxC) return hipErrorNotSupported;
+    const long long chunks = (long long)nx * ny * ((nz + zc - 1) / zc);
+    if (C > kLapMaxC) return hipErrorNotSupported;
+    const int blocks = (int)std::min<long long>(chunks, kReduceBlocks);
     const size_t lds = sizeof(float) * (size_t)(zc + 2) * C;
     const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(work) |
                           reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
-    hipLaunchKernelGGL(k_laplacian<false>, dim3((unsigned)blocks), dim3(256), lds, st, c, nx, ny, nz, C, zc, work,
-                       0.0f, lam, value, aligned);
-    hipLaunchKernelGGL(k_laplacian<true>, dim3((unsigned)blocks), dim3(256), lds, st, work, nx, ny, nz, C, zc, grad,
-                       (float)(2.0 * lam), 0.0, nullptr, aligned);
+    hipLaunchKernelGGL(k_laplacian<false>, dim3(blocks), dim3(256), lds, st, c, nx, ny, nz, C, zc, work, 0.0f,
+                       value ? partials : nullptr, aligned);
+    if (value) {
+        hipError_t e = launch_sum_partials(partials, blocks, value, lam, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_laplacian<true>, dim3(blocks), dim3(256), lds, st, work, nx, ny, nz, C, zc, grad,
+                       (float)(2.0 * lam), nullptr, aligned);
     return hipGetLastError();
 }
 
@@ -106,7 +118,7 @@ __device__ __forceinline__ double huber_h(float x, float delta)
 }
 
 __global__ __launch_bounds__(256) void k_huber(const float *__restrict__ c, long long n, float delta, float lam,
-                                               float *__restrict__ grad, double *__restrict__ value, int aligned)
+                                               float *__restrict__ grad, double *__restrict__ partials, int aligned)
 {
     __shared__ double ws[4];
     const float inv = 1.0f / delta;
@@ -128,19 +140,20 @@ __global__ __launch_bounds__(256) void k_huber(const float *__restrict__ c, long
         hs += huber_h(x, delta);
         grad[e] = fmaf(lam, fminf(1.0f, fmaxf(-1.0f, x * inv)), grad[e]);
     }
-    if (value) {
+    if (partials) {
         const double t = block_sum(hs, ws);
-        if (threadIdx.x == 0) atomicAdd(value, (double)lam * t);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
     }
 }
 
 hipError_t launch_huber_reg(const float *c, long long n, double delta, double lam, float *grad, double *value,
-                            hipStream_t st)
+                            double *partials, hipStream_t st)
 {
     const int aligned = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
-    const int blocks = (int)std::min<long long>((n / 4 + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_huber, dim3(std::max(blocks, 1)), dim3(256), 0, st, c, n, (float)delta, (float)lam, grad,
-                       value, aligned);
+    const int blocks = std::max(1, (int)std::min<long long>((n / 4 + 255) / 256, kReduceBlocks));
+    hipLaunchKernelGGL(k_huber, dim3(blocks), dim3(256), 0, st, c, n, (float)delta, (float)lam, grad,
+                       value ? partials : nullptr, aligned);
+    if (value) return launch_sum_partials(partials, blocks, value, (double)(float)lam, 1, st);
     return hipGetLastError();
 }
 
@@ -148,7 +161,7 @@ hipError_t launch_huber_reg(const float *c, long long n, double delta, double la
 // gradient), value += sum w h(r).
 __global__ __launch_bounds__(256) void k_huber_loss(const float *__restrict__ I, const float *__restrict__ data,
                                                     const float *__restrict__ w, long long n, float delta,
-                                                    float *__restrict__ y, double *__restrict__ value)
+                                                    float *__restrict__ y, double *__restrict__ partials)
 {
     __shared__ double ws[4];
     const float inv = 1.0f / delta;
@@ -158,23 +171,25 @@ __global__ __launch_bounds__(256) void k_huber_loss(const float *__restrict__ I,
         hs += (double)wt * (a <= delta ? 0.5 * (double)r * (double)r / (double)delta : (double)a - 0.5 * (double)delta);
         y[e] = wt * fminf(1.0f, fmaxf(-1.0f, r * inv));
     }
-    if (value) {
+    if (partials) {
         const double t = block_sum(hs, ws);
-        if (threadIdx.x == 0) atomicAdd(value, t);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
     }
 }
 
 hipError_t launch_huber_loss(const float *I, const float *data, const float *w, long long n, double delta, float *y,
-                             double *value, hipStream_t st)
+                             double *value, double *partials, hipStream_t st)
 {
-    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_huber_loss, dim3(std::max(blocks, 1)), dim3(256), 0, st, I, data, w, n, (float)delta, y, value);
+    const int blocks = std::max(1, (int)std::min<long long>((n + 255) / 256, kReduceBlocks));
+    hipLaunchKernelGGL(k_huber_loss, dim3(blocks), dim3(256), 0, st, I, data, w, n, (float)delta, y,
+                       value ? partials : nullptr);
+    if (value) return launch_sum_partials(partials, blocks, value, 1.0, 1, st);
     return hipGetLastError();
 }
 
 // value += scale * sum x^2 (float64)
-__global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ x, long long n, double scale,
-                                               double *__restrict__ value)
+__global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ x, long long n,
+                                               double *__restrict__ partials)
 {
     __shared__ double ws[4];
     double ss = 0.0;
@@ -183,14 +198,14 @@ __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ x, long
         ss += v * v;
     }
     const double t = block_sum(ss, ws);
-    if (threadIdx.x == 0) atomicAdd(value, scale * t);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, hipStream_t st)
+hipError_t launch_sumsq(const float *x, long long n, double scale, double *value, double *partials, hipStream_t st)
 {
-    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_sumsq, dim3(std::max(blocks, 1)), dim3(256), 0, st, x, n, scale, value);
-    return hipGetLastError();
+    const int blocks = std::max(1, (int)std::min<long long>((n + 255) / 256, kReduceBlocks));
+    hipLaunchKernelGGL(k_sumsq, dim3(blocks), dim3(256), 0, st, x, n, partials);
+    return launch_sum_partials(partials, blocks, value, scale, 1, st);
 }
 
 // c_new = y - step p g; y = c_new + m (c_new - c); c = c_new, with p a

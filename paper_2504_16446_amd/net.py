@@ -38,13 +38,13 @@ def bf16_empty(shape, device):
     return torch.empty(shape, dtype=torch.int16, device=device)
 
 
-def pack_bf16(x: torch.Tensor, cpad: int, shift=None, scale=None) -> torch.Tensor:
-    """float32 [..., cin] -> bf16 bits [..., cpad] (optionally (x - shift) * scale)."""
+def pack_bf16(x: torch.Tensor, cpad: int, shift=None, scale=None, pre=1.0) -> torch.Tensor:
+    """float32 [..., cin] -> bf16 bits [..., cpad] of (pre x - shift) * scale."""
     assert x.dtype == torch.float32 and x.is_contiguous()
     cin = x.shape[-1]
     nvox = x.numel() // cin
     out = bf16_empty(x.shape[:-1] + (cpad,), x.device)
-    call("tt_pack_bf16", _p(x), nvox, cin, cpad, _p(shift), _p(scale), _p(out), _stream(x.device))
+    call("tt_pack_bf16", _p(x), nvox, cin, cpad, float(pre), _p(shift), _p(scale), _p(out), _stream(x.device))
     return out
 
 
@@ -131,9 +131,16 @@ class WarmStartNet:
     def n_params(self):
         return sum(int((l.w != 0).sum()) for l in self.layers) + sum(l.b.numel() for l in self.layers) - 4
 
-    def prepare_input(self, x28: torch.Tensor) -> torch.Tensor:
-        """float32 [..., 28] normalised backprojection -> standardised bf16 [..., 32]."""
-        return pack_bf16(x28.contiguous(), 32, self.in_shift, self.in_scale)
+    def prepare_input(self, x28: torch.Tensor, pre=1.0) -> torch.Tensor:
+        """float32 [..., 28] backprojection (scaled by pre = 1 / kappa) -> standardised bf16 [..., 32]."""
+        return pack_bf16(x28.contiguous(), 32, self.in_shift, self.in_scale, pre)
+
+    def set_input_statistics(self, x28: torch.Tensor, pre=1.0):
+        """Standardisation from the channel means and standard deviations of pre * x28."""
+        nvox = x28.numel() // CHANNELS[0]
+        work = torch.empty(int(lib().tt_channel_stats_work_len()), dtype=torch.float64, device=self.device)
+        call("tt_channel_stats", _p(x28), nvox, CHANNELS[0], CHANNELS[0], float(pre), _p(self.in_shift),
+             _p(self.in_scale), _p(work), work.numel(), _stream(self.device))
 
     def forward(self, xb: torch.Tensor, keep=False):
         acts = [xb]

@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import Geometry, call, lib
 
 __all__ = ["Projector", "ProjectFn", "project", "LBFGS", "sh_eval", "num_coeffs", "tensor_properties",
-           "PROPERTY_FIELDS", "laplacian_reg", "huber_reg", "GradientDescent"]
+           "PROPERTY_FIELDS", "laplacian_reg", "huber_reg", "sumsq", "GradientDescent"]
 
 
 def num_coeffs(ell_max: int) -> int:
@@ -57,7 +57,8 @@ class Projector:
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame=None, n_sub=3, step=1.0,
                  seg_span=2 * math.pi, joff=None, koff=None, map_precision="fp32", device=None,
-                 model="trilinear", basis="sh", dirs=None, width=None):
+                 model="trilinear", basis="sh", dirs=None, width=None, forward_batch=None,
+                 workspace_budget=None):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("Projector runs on a HIP device only")
@@ -99,7 +100,21 @@ class Projector:
         call("tt_set_projector", self._h,
              _lib.TT_PROJ_JOSEPH if model == "joseph" else _lib.TT_PROJ_TRILINEAR)
         self.model = model
-        sizes = (C.c_int64 * 6)()
+        # Workspace (device memory owned here, handed to the library): the
+        # forward maps `forward_batch` projections per pass; by default as many
+        # as fit a budget of 1/8 of the free device memory, clamped to [1, 24] GiB.
+        sizes = (C.c_int64 * 8)()
+        call("tt_sizes", self._h, sizes)
+        per_proj = int(sizes[7])
+        if forward_batch is None:
+            if workspace_budget is None:
+                free, _ = torch.cuda.mem_get_info(self.device)
+                workspace_budget = min(24 << 30, max(1 << 30, free // 8))
+            forward_batch = max(1, int(workspace_budget) // per_proj)
+        nbytes = int(call("tt_workspace_bytes", self._h, int(min(forward_batch, g.n_proj))))
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._bind_stream()
+        call("tt_set_workspace", self._h, C.c_void_p(self._ws.data_ptr()), nbytes)
         call("tt_sizes", self._h, sizes)
         self.n = tuple(int(v) for v in n)
         self.ell_max, self.n_proj = int(ell_max), g.n_proj
@@ -146,6 +161,12 @@ class Projector:
         call("tt_timing_read", self._h, ms, n)
         return {k: (ms[i], int(n[i])) for i, k in enumerate(_lib.KERNEL_CLASSES)}
 
+    def ray_samples(self) -> int:
+        """Ray samples (or Joseph cuts) of all projections that touch the volume."""
+        out = C.c_int64(0)
+        call("tt_ray_samples", self._h, C.byref(out))
+        return int(out.value)
+
     def basis_matrix(self) -> np.ndarray:
         B = np.empty((self.n_proj, self.n_seg, self.n_coeff))
         call("tt_basis_matrix", self._h, _dptr(B))
@@ -173,6 +194,19 @@ class Projector:
         self._bind_stream()
         call("tt_adjoint", self._h, py, po, float(beta), pcv)
         return out
+
+    def _normal_work(self):
+        n = int(call("tt_normal_work_bytes", self._h))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def kappa(self, radius: float) -> float:
+        """Lower median over the voxels within `radius` of the centre of (A^T A u)_{v,0},
+        u the unit isotropic field (the network-input scale; synchronises)."""
+        work = self._normal_work()
+        out = C.c_double(0.0)
+        self._bind_stream()
+        call("tt_kappa", self._h, float(radius), C.c_void_p(work.data_ptr()), work.numel(), C.byref(out))
+        return out.value
 
     def loss_grad(self, c, data, w=None, mu=0.0, want_resid=True):
         """(loss[1] float64, grad, resid) of sum w (Ac - I)^2 + mu sum c^2."""
@@ -210,8 +244,11 @@ class LBFGS:
 
     def __init__(self, projector: Projector, m: int = 10):
         self.projector = projector
+        nbytes = int(call("tt_lbfgs_workspace_bytes", projector._h, int(m)))
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=projector.device)
         h = C.c_void_p()
-        call("tt_lbfgs_create", projector._h, int(m), C.byref(h))
+        projector._bind_stream()
+        call("tt_lbfgs_create", projector._h, int(m), C.c_void_p(self._ws.data_ptr()), nbytes, C.byref(h))
         self._h = h
         self.m = m
         self._refs = None
@@ -244,6 +281,12 @@ class LBFGS:
         pd = _f32(d, p.vol_shape, "d", p.device)
         p._bind_stream()
         call("tt_lbfgs_step_direction", self._h, pd)
+
+    def refresh(self):
+        """Recompute the residual A c - I with an explicit forward projection (the
+        iterations update it incrementally); query() then reports it."""
+        self.projector._bind_stream()
+        call("tt_lbfgs_refresh", self._h)
 
     def query(self):
         """(loss, ||r||, ||I||, accepted pairs); synchronises."""
@@ -297,6 +340,26 @@ def _stream(t):
     return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
+_PARTIALS = {}
+
+
+def _partials(device):
+    """float64 partial-sum buffer (TT_REDUCE_WORK elements) for value reductions on this device."""
+    key = torch.device(device)
+    buf = _PARTIALS.get(key)
+    if buf is None:
+        buf = _PARTIALS[key] = torch.empty(_lib.REDUCE_WORK, dtype=torch.float64, device=key)
+    return C.c_void_p(buf.data_ptr()), buf.numel()
+
+
+def sumsq(x: torch.Tensor, value: torch.Tensor, scale: float = 1.0):
+    """value[0] += scale * sum x^2 (float64, fixed summation order)."""
+    _dev_f32(x, "x")
+    pp, pn = _partials(x.device)
+    call("tt_sumsq", C.c_void_p(x.data_ptr()), x.numel(), float(scale), C.c_void_p(value.data_ptr()), pp, pn,
+         _stream(x))
+
+
 def _dev_f32(t, name):
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous float32 device tensor")
@@ -321,8 +384,9 @@ def laplacian_reg(c: torch.Tensor, lam: float, grad: torch.Tensor, value: torch.
             raise ValueError("value must be a float64 device tensor")
         vp = C.c_void_p(value.data_ptr())
     nx, ny, nz, nc = (int(v) for v in c.shape)
+    pp, pn = _partials(c.device)
     call("tt_laplacian_reg", C.c_void_p(c.data_ptr()), nx, ny, nz, nc, float(lam), C.c_void_p(work.data_ptr()),
-         C.c_void_p(grad.data_ptr()), vp, _stream(c))
+         C.c_void_p(grad.data_ptr()), vp, pp, pn, _stream(c))
     return work
 
 
@@ -337,8 +401,9 @@ def huber_reg(c: torch.Tensor, delta: float, lam: float, grad: torch.Tensor, val
         if value.dtype != torch.float64 or not value.is_cuda:
             raise ValueError("value must be a float64 device tensor")
         vp = C.c_void_p(value.data_ptr())
+    pp, pn = _partials(c.device)
     call("tt_huber_reg", C.c_void_p(c.data_ptr()), c.numel(), float(delta), float(lam), C.c_void_p(grad.data_ptr()),
-         vp, _stream(c))
+         vp, pp, pn, _stream(c))
 
 
 class GradientDescent:
@@ -360,12 +425,13 @@ class GradientDescent:
     def voxel_preconditioner(projector: Projector, floor: float = 1e-6) -> torch.Tensor:
         """Diagonal preconditioner 1 / (A^T A u)_{v,0} per voxel (all coefficients of a
         voxel share it), u the unit isotropic field: the normal operator's scale at
-        each voxel, floored at floor times its maximum."""
-        u = torch.zeros(projector.vol_shape, device=projector.device)
-        u[..., 0] = 1.0
-        d = projector.adjoint(projector.forward(u))[..., :1]
-        d = d.clamp_min(floor * float(d.max()))
-        return (1.0 / d).expand(projector.vol_shape).contiguous()
+        each voxel, floored at floor times its maximum (computed by the library)."""
+        p = torch.empty(projector.vol_shape, device=projector.device)
+        work = projector._normal_work()
+        projector._bind_stream()
+        call("tt_voxel_preconditioner", projector._h, float(floor), C.c_void_p(p.data_ptr()),
+             C.c_void_p(work.data_ptr()), work.numel())
+        return p
 
     def objective_grad(self, c, data, w=None, mu=0.0, work=None):
         """(value float64[1], grad) of the whole objective at c."""
@@ -379,12 +445,12 @@ class GradientDescent:
             I = self.P.forward(c)
             loss = torch.zeros(1, dtype=torch.float64, device=c.device)
             y = torch.empty_like(I)
+            pp, pn = _partials(c.device)
             call("tt_huber_loss", C.c_void_p(I.data_ptr()), C.c_void_p(data.data_ptr()),
                  C.c_void_p(w.data_ptr()) if w is not None else None, I.numel(), self.loss_delta,
-                 C.c_void_p(y.data_ptr()), C.c_void_p(loss.data_ptr()), _stream(c))
+                 C.c_void_p(y.data_ptr()), C.c_void_p(loss.data_ptr()), pp, pn, _stream(c))
             if mu:
-                call("tt_sumsq", C.c_void_p(c.data_ptr()), c.numel(), float(mu), C.c_void_p(loss.data_ptr()),
-                     _stream(c))
+                sumsq(c, loss, mu)
             grad = self.P.adjoint(y, beta=2.0 * mu, c=c)
         if self.lam_lap:
             laplacian_reg(c, self.lam_lap, grad, loss, work)

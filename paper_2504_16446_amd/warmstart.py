@@ -5,10 +5,14 @@ The paper's outlook (section 4) names simulated data for training
 machine-learning models; here such data trains a small 3-D convolutional
 network that maps the normalised backprojection of the measured data to
 initial SH coefficients, which L-BFGS then refines.  Zero-initialised L-BFGS
-is the fallback (taken when the prediction does not lower the loss), and the
-final data residual decides whether it helped.
+is the fallback (taken when the prediction is zero or not finite; a poor but
+finite prediction costs at most the one iteration whose exact line search
+scales it), and the final data residual, recomputed with an explicit forward
+projection, decides whether it helped.
 
-Pipeline (every numerical step runs in libtt_hip.so):
+Pipeline (the projections, the scale kappa, the statistics, the network and
+the tiling run in libtt_hip.so; torch supplies memory, the seeded phantoms'
+rasterisation and the noise draws, which are inputs):
   1. x = A^T I / kappa, with kappa the median over the support of
      (A^T A u)_{v,00} for the unit isotropic field u: one scale per geometry,
      insensitive to the number of projections and segments;
@@ -45,7 +49,7 @@ import tt_inputs as synth
 
 from . import net
 from ._lib import call
-from .projector import LBFGS, Projector, sh_eval
+from .projector import LBFGS, Projector, sh_eval, sumsq
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_c4.npz")
@@ -93,21 +97,19 @@ def bundle_phantom(w: synth.Workload, seed: int, device, background=0.1):
 
 
 def kappa(P: Projector, radius: float) -> float:
-    """Median over the support ball of (A^T A u)_{v,00} for u_{v,00} = 1."""
-    u = torch.zeros(P.vol_shape, device=P.device)
-    u[..., 0] = 1.0
-    g = P.adjoint(P.forward(u))
-    ax = [torch.arange(m, device=P.device, dtype=torch.float32) - (m - 1) / 2.0 for m in P.n]
-    X, Y, Z = torch.meshgrid(*ax, indexing="ij")
-    ball = (X * X + Y * Y + Z * Z) <= radius ** 2
-    return float(g[..., 0][ball].median())
+    """Lower median over the support ball of (A^T A u)_{v,00} for u_{v,00} = 1 (library)."""
+    return P.kappa(radius)
 
 
 # ---------------------------------------------------------------------------
 # training set and training
 # ---------------------------------------------------------------------------
 def synthesize(w: synth.Workload, seeds, device, log_every=256):
-    """(inputs [n, X, Y, Z, 28] float32, targets [n, X, Y, Z, 28] float32, kappa)."""
+    """(backprojections [n, X, Y, Z, 28] float32, targets [n, X, Y, Z, 28] float32, kappa).
+
+    The network input is the backprojection scaled by 1 / kappa; the scale is
+    applied by the statistics and packing kernels, so the stored arrays are
+    copies of the library's outputs."""
     P = Projector.from_workload(w, device=device)
     kap = kappa(P, w.radius)
     n = len(seeds)
@@ -124,8 +126,8 @@ def synthesize(w: synth.Workload, seeds, device, log_every=256):
             sigma = w.noise * float(I.abs().max())
             I.add_(torch.randn(I.shape, generator=gen, device=device), alpha=sigma)
         P.adjoint(I, out=g)
-        Xs[i] = g[..., :NET_CH] / kap
-        Ts[i] = c[..., :NET_CH]
+        Xs[i].copy_(g[..., :NET_CH])
+        Ts[i].copy_(c[..., :NET_CH])
         if log_every and (i + 1) % log_every == 0:
             _log("synthesised", n=i + 1, of=n)
     return Xs, Ts, kap
@@ -137,13 +139,9 @@ def train(w: synth.Workload, n_phantoms=4096, epochs=20, batch=8, lr=1e-3, devic
     Xs, Ts, kap = synthesize(w, np.arange(n_phantoms), dev)
     _log("training set ready", seconds=round(time.time() - t0, 2), kappa=kap)
     model = net.WarmStartNet(dev, seed=seed)
-    flat = Xs.reshape(-1, NET_CH)
-    mean = flat.mean(0)
-    std = flat.std(0).clamp_min(1e-12)
-    model.in_shift.copy_(mean)
-    model.in_scale.copy_(1.0 / std)
-    Xb = model.prepare_input(Xs)  # bf16 [n, X, Y, Z, 32]
-    del Xs, flat
+    model.set_input_statistics(Xs, pre=1.0 / kap)
+    Xb = model.prepare_input(Xs, pre=1.0 / kap)  # bf16 [n, X, Y, Z, 32]
+    del Xs
     torch.cuda.empty_cache()
     rng = np.random.default_rng(seed + 1)
     nvox = batch * w.n_vox
@@ -195,8 +193,7 @@ def tile_origins(n, T=TILE, overlap=OVERLAP):
 def predict(model: net.WarmStartNet, P: Projector, data: torch.Tensor, kap: float, batch=8):
     """Warm-start coefficients [nx, ny, nz, C]: network on the normalised backprojection."""
     dev = P.device
-    x = P.adjoint(data)
-    x.mul_(1.0 / kap)
+    x = P.adjoint(data)  # scaled by 1 / kap inside the tile gather
     C_out = P.n_coeff
     orig = [tile_origins(m) for m in P.n]
     ot = [torch.tensor(o, dtype=torch.int32, device=dev) for o in orig]
@@ -208,7 +205,7 @@ def predict(model: net.WarmStartNet, P: Projector, data: torch.Tensor, kap: floa
     for t0 in range(0, ntiles, batch):
         nt = min(batch, ntiles - t0)
         call("tt_tile_gather", p(x), *P.n, C_out, NET_CH, 32, p(ot[0]), len(orig[0]), p(ot[1]), len(orig[1]),
-             p(ot[2]), len(orig[2]), TILE, p(model.in_shift), p(model.in_scale), t0, nt, p(xb), s)
+             p(ot[2]), len(orig[2]), TILE, float(1.0 / kap), p(model.in_shift), p(model.in_scale), t0, nt, p(xb), s)
         y = model.forward(xb[:nt])
         ytiles[t0:t0 + nt].copy_(y)
     c0 = torch.empty(P.vol_shape, device=dev)
@@ -220,8 +217,10 @@ def predict(model: net.WarmStartNet, P: Projector, data: torch.Tensor, kap: floa
 def lbfgs_to(P: Projector, data, mu, c, target_rel, max_iter, log_every=10, label="", first_direction=None):
     """Run L-BFGS from c (in place) until ||Ac - I|| / ||I|| <= target_rel.
 
-    With first_direction, the first iteration searches along that direction
-    (exact line search) instead of the steepest-descent direction."""
+    The stop test reads the solver's running residual; the returned final
+    residual is recomputed from an explicit forward projection of c.  With
+    first_direction, the first iteration searches along that direction (exact
+    line search) instead of the steepest-descent direction."""
     solver = LBFGS(P, m=10)
     solver.init(c, data, None, mu)
     loss, rn, In, _ = solver.query()
@@ -239,7 +238,9 @@ def lbfgs_to(P: Projector, data, mu, c, target_rel, max_iter, log_every=10, labe
         it += 1
         if log_every and it % log_every == 0:
             _log(f"{label} iteration", it=it, rel_resid=rel)
-    return it, rel0, rel, solver
+    solver.refresh()
+    _, rn, In, _ = solver.query()
+    return it, rel0, rn / In, solver
 
 
 def warm_start(model, P, data, kap=None, radius=None):
@@ -252,7 +253,10 @@ def warm_start(model, P, data, kap=None, radius=None):
     if kap is None:
         kap = kappa(P, radius)
     c0 = predict(model, P, data, kap)
-    if not bool(torch.isfinite(c0).all()) or float(c0.abs().max()) == 0.0:
+    ss = torch.zeros(1, dtype=torch.float64, device=P.device)
+    sumsq(c0, ss)
+    n2 = float(ss.item())
+    if not math.isfinite(n2) or n2 == 0.0:
         return None, kap, True
     return c0, kap, False
 
@@ -320,7 +324,6 @@ def holdout(model, w: synth.Workload, seeds, plain_iters=30, device="cuda:0"):
         _, rn, In, _ = s.query()
         target = rn / In
         c0, _, fb = warm_start(model, P, data, kap=kap)
-        err_net = float((c0[..., :NET_CH] - c_true[..., :NET_CH]).norm() / c_true[..., :NET_CH].norm())
         c = torch.zeros(P.vol_shape, device=dev)
         it_w, _, rel_w, s2 = lbfgs_to(P, data, w.mu, c, target, 4 * plain_iters, log_every=0, first_direction=c0)
         # relative residual right after the step along the prediction
@@ -328,7 +331,7 @@ def holdout(model, w: synth.Workload, seeds, plain_iters=30, device="cuda:0"):
         _, _, rel1, _ = lbfgs_to(P, data, w.mu, c1, 0.0, 1, log_every=0, first_direction=c0)
         rows.append({"seed": int(seed), "target": target, "zero_init_rel_resid": rel_zero0,
                      "warm_rel_resid_after_first_step": rel1, "warm_iterations": it_w,
-                     "plain_iterations": plain_iters, "net_coeff_rel_error": err_net, "fallback": fb})
+                     "plain_iterations": plain_iters, "fallback": fb})
         _log("holdout", **rows[-1])
     return rows
 

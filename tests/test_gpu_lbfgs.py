@@ -85,3 +85,48 @@ def test_lbfgs_stops_at_tolerance_and_steps_async():
     for _ in range(3):
         solver.step()  # asynchronous
     assert solver.query()[0] <= loss0
+
+
+def _golden_c2():
+    import importlib.util
+    import json
+    import os
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_lbfgs_c2_subset",
+                                                  os.path.join(gold, "make_lbfgs_c2_subset.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(gold, "lbfgs_c2_subset.json")) as f:
+        return mod, json.load(f)
+
+
+def test_lbfgs_c2_subset_fifty_iterations_match_oracle():
+    """100^3 / ell_max 8 workload on every tenth projection, 50 iterations from zero:
+    the final relative residual, recomputed with an explicit forward projection, is
+    within 1% of the float64 oracle's (stored by tests/golden/make_lbfgs_c2_subset.py);
+    the loss history and sampled coefficients are compared and reported."""
+    mod, rec = _golden_c2()
+    og, w, data = mod.problem()
+    P = gpu_projector(og)
+    solver = LBFGS(P, m=10)
+    c = torch.zeros(og.vol_shape, device=DEV)
+    solver.init(c, _t(data), None, w.mu)
+    n, hist = solver.run(rec["iterations"])
+    assert n == rec["iterations"] == 50
+    solver.refresh()
+    _, rn, In, _ = solver.query()
+    r = P.forward(c).double() - _t(data).double()
+    final = float(r.norm() / _t(data).double().norm())
+    ref = rec["final_rel_residual_explicit"]
+    loss_ref = np.asarray(rec["loss"])
+    idx = mod.sample_indices(c.numel())
+    cs = c.reshape(-1)[torch.from_numpy(idx).to(DEV)].double().cpu().numpy()
+    c_err = rel_l2(cs, np.asarray(rec["sample_values"]))
+    norm_err = abs(float(c.double().norm()) / rec["c_norm"] - 1)
+    print(f"final rel residual {final:.6e} (refreshed {rn / In:.6e}) vs oracle {ref:.6e}; "
+          f"loss max rel diff {np.abs(hist[:, 0] / loss_ref - 1).max():.2e}; "
+          f"sampled c rel-L2 {c_err:.2e}; |c| rel diff {norm_err:.2e}")
+    assert abs(final / ref - 1) <= 0.01
+    assert abs(rn / In / final - 1) <= 1e-4
+    assert np.abs(hist[:, 0] / loss_ref - 1).max() <= 1e-3
+    assert c_err <= 1e-2

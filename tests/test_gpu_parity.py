@@ -46,6 +46,8 @@ CASES = {
     "small_l8_seg16": lambda: small(ell_max=8, n_seg=16),
     "small_l6_seg8": lambda: small(ell_max=6),
     "small_l0": lambda: small(ell_max=0, n_seg=4),
+    "small_l10": lambda: small(ell_max=10),                 # C = 66: streamed map (Cp 80), 5 adjoint tiles
+    "small_l12_seg16": lambda: small(ell_max=12, n_seg=16),  # C = 91: Cp 96, 6 adjoint tiles, 8 unique segments
     "half_circle_segments": _half_circle,   # no antipodal folding: 6 distinct segments
     "steep_tilts": lambda: steep(),          # forward march gathers these rays from global memory
     "degenerate": lambda: degenerate(),      # 1-voxel-thick volume, one detector row, 2 segments
@@ -136,16 +138,38 @@ def test_repeat_determinism():
 
 
 def test_forward_batches_agree():
-    # the same geometry with a tiny forward batch (many batches) gives identical results
-    import os
+    # the same geometry with the smallest forward batch (many batches) gives identical results
     og = small(ell_max=4)
     c, _ = _inputs(og, 8)
     P1 = gpu_projector(og)
-    os.environ["TT_FORWARD_BATCH_BYTES"] = "1"
-    try:
-        P2 = gpu_projector(og)
-    finally:
-        del os.environ["TT_FORWARD_BATCH_BYTES"]
-    assert P2.batch <= 4 and P1.batch == og.n_proj
+    P2 = gpu_projector(og, forward_batch=1)
+    assert P2.batch == 4 and P1.batch == og.n_proj
     assert torch.equal(P1.forward(_t(c)), P2.forward(_t(c)))
+
+
+def test_workspace_is_required_and_sized():
+    import ctypes as C
+    from paper_2504_16446_amd._lib import TTError, call, lib
+    og = small(ell_max=4)
+    P = gpu_projector(og)
+    h = C.c_void_p()
+    with torch.cuda.device(DEV):
+        call("tt_create", C.byref(P.geometry), C.byref(h))
+    try:
+        c = _t(_inputs(og, 9)[0])
+        I = torch.empty(og.data_shape, device=DEV)
+        with pytest.raises(TTError):  # no workspace attached
+            call("tt_project", h, C.c_void_p(c.data_ptr()), C.c_void_p(I.data_ptr()))
+        small_ws = int(call("tt_workspace_bytes", h, 1))
+        full_ws = int(call("tt_workspace_bytes", h, og.n_proj))
+        assert full_ws > small_ws > 0
+        ws = torch.empty(small_ws - 256, dtype=torch.uint8, device=DEV)
+        with pytest.raises(TTError):  # below the minimum
+            call("tt_set_workspace", h, C.c_void_p(ws.data_ptr()), ws.numel())
+        ws = torch.empty(full_ws, dtype=torch.uint8, device=DEV)
+        call("tt_set_workspace", h, C.c_void_p(ws.data_ptr()), ws.numel())
+        call("tt_project", h, C.c_void_p(c.data_ptr()), C.c_void_p(I.data_ptr()))
+        assert torch.equal(I, P.forward(c))
+    finally:
+        lib().tt_destroy(h)
 

@@ -2,11 +2,16 @@
 fp32 accumulation (forward: c and B rounded to bf16; adjoint: the backprojected
 segment values Q_s and B rounded to bf16).
 
-Parity: against the float64 oracle evaluated with the same rounding points
-(relative L2 <= 2e-5: both sides round identical float32 inputs, but the
-adjoint's Q is an intermediate, so a value within an fp32 rounding of a bf16
-tie may round the other way).  The error against the unrounded float64 oracle
-is reported and bounded by the bf16 unit roundoff scale (<= 1e-2).
+Parity: against the float64 oracle evaluated with the same rounding points.
+Forward: relative L2 <= 1e-5 (both sides round the same float32 inputs c and
+B; products of two bf16 values are exact in fp32, so only fp32 accumulation
+separates them).  Adjoint: relative L2 <= 2e-5, because its rounding point Q
+is an intermediate: a value within an fp32 rounding (~1e-7 relative) of a
+bf16 rounding boundary rounds the other way with probability p ~ 2^-23 / 2^-8
+~ 3e-5, which moves that element by one bf16 unit (2^-8 relative); such flips
+add incoherently, giving ~sqrt(p) 2^-8 ~ 2e-5 relative L2 in the worst case.
+The error against the unrounded float64 oracle is reported and bounded by the
+bf16 unit roundoff scale (<= 1e-2).
 """
 import numpy as np
 import pytest
@@ -26,10 +31,11 @@ def _t(a):
 
 def _geom(name):
     return {"small_l4": lambda: small(ell_max=4), "small_l8_seg16": lambda: small(ell_max=8, n_seg=16),
-            "small_l6": lambda: small(ell_max=6), "c1": lambda: workload("c1")}[name]()
+            "small_l6": lambda: small(ell_max=6), "c1": lambda: workload("c1"),
+            "small_l10": lambda: small(ell_max=10)}[name]()
 
 
-@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1"])
+@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1", "small_l10"])
 def test_bf16_forward(name):
     og = _geom(name)
     rng = np.random.default_rng(41)
@@ -42,14 +48,14 @@ def test_bf16_forward(name):
     got = P.forward(_t(c)).cpu().numpy()
     e_r, e = rel_l2(got, ref_rounded), rel_l2(got, ref)
     print(f"{name} bf16 forward: vs rounded oracle {e_r:.2e}, vs float64 oracle {e:.2e}")
-    assert e_r <= 2e-5
+    assert e_r <= 1e-5
     assert e <= 1e-2
     # the fp32 tier on the same projector object
     P.set_precision("fp32")
     assert rel_l2(P.forward(_t(c)).cpu().numpy(), ref) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1"])
+@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1", "small_l10"])
 def test_bf16_adjoint(name):
     og = _geom(name)
     rng = np.random.default_rng(42)

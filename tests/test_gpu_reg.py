@@ -15,7 +15,7 @@ from helpers import gpu_projector, rel_l2
 from oracle.regularizers import gradient_descent, huber_reg as o_huber, laplacian, laplacian_reg as o_lap
 import tt_inputs as synth
 from paper_2504_16446_amd import phantom
-from paper_2504_16446_amd.projector import GradientDescent, huber_reg, laplacian_reg
+from paper_2504_16446_amd.projector import GradientDescent, huber_reg, laplacian_reg, sumsq
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -129,3 +129,18 @@ def test_preconditioned_descent_parity():
     assert np.all(np.abs(losses - losses_ref) <= 1e-5 * np.abs(losses_ref))
     assert rel_l2(c.cpu().numpy(), c_ref) <= 1e-5
     assert losses[-1] < losses[0]
+
+
+def test_regulariser_values_repeat_bit_for_bit():
+    # fixed-order float64 partial sums: the same inputs give the same value every time
+    rng = np.random.default_rng(31)
+    ct = torch.tensor(rng.standard_normal((37, 29, 41, 15)).astype(np.float32), device=DEV)
+    vals = []
+    for _ in range(3):
+        val = torch.zeros(1, dtype=torch.float64, device=DEV)
+        g = torch.zeros_like(ct)
+        laplacian_reg(ct, 0.3, g, val)
+        huber_reg(ct, 0.2, 1.1, g, val)
+        sumsq(ct, val, 0.7)
+        vals.append(float(val.item()))
+    assert vals[0] == vals[1] == vals[2]

@@ -39,7 +39,7 @@ def test_tiles_roundtrip(n):
     s = C.c_void_p(torch.cuda.current_stream(DEV).cuda_stream)
     tiles = net.bf16_empty((ntiles, T, T, T, 32), DEV)
     call("tt_tile_gather", _p(x), *n, 45, 28, 32, _p(ot[0]), len(orig[0]), _p(ot[1]), len(orig[1]), _p(ot[2]),
-         len(orig[2]), T, None, None, 0, ntiles, _p(tiles), s)
+         len(orig[2]), T, 1.0, None, None, 0, ntiles, _p(tiles), s)
     yt = net.bf16_to_float(tiles).contiguous()
     out = torch.empty(n + (45,), device=DEV)
     call("tt_tile_blend", _p(yt), 32, 28, *n, _p(ot[0]), len(orig[0]), _p(ot[1]), len(orig[1]), _p(ot[2]),
@@ -47,6 +47,51 @@ def test_tiles_roundtrip(n):
     ref = net.bf16_to_float(net.pack_bf16(x[..., :28].contiguous(), 28))
     assert torch.allclose(out[..., :28], ref, rtol=1e-6, atol=1e-6)
     assert torch.all(out[..., 28:] == 0)
+
+
+def test_kappa_matches_oracle():
+    """kappa = lower median over the support ball of (A^T A u)_{v,0} (exact selection)."""
+    import oracle
+    w = synth.WORKLOADS["c1"]
+    og = oracle.Geometry.from_workload(w)
+    u = np.zeros(og.vol_shape)
+    u[..., 0] = 1.0
+    d = oracle.adjoint(og, oracle.project(og, u))[..., 0]
+    ax = [np.arange(m) - (m - 1) / 2.0 for m in og.n]
+    X, Y, Z = np.meshgrid(*ax, indexing="ij")
+    for radius in (w.radius, 5.0, 0.0):
+        vals = np.sort(d[(X * X + Y * Y + Z * Z) <= radius * radius])
+        ref = vals[(len(vals) - 1) // 2] if len(vals) else None
+        P = warmstart.Projector.from_workload(w, device=DEV)
+        if ref is None:
+            with pytest.raises(Exception):
+                P.kappa(radius)
+            continue
+        k = P.kappa(radius)
+        print("kappa", radius, k, ref)
+        assert abs(k / ref - 1) <= 1e-5
+    # the selection itself is exact: the GPU value is one of the GPU field's ball values
+    g = P.adjoint(P.forward(torch.tensor(u.astype(np.float32), device=DEV)))[..., 0].cpu().numpy()
+    gv = np.sort(g[(X * X + Y * Y + Z * Z) <= w.radius ** 2])
+    assert P.kappa(w.radius) == float(gv[(len(gv) - 1) // 2])
+
+
+def test_channel_statistics_match_float64():
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal((3, 10, 11, 12, 28)) * rng.uniform(0.1, 5, 28) + rng.uniform(-2, 2, 28))
+    x = x.astype(np.float32)
+    model = net.WarmStartNet(DEV)
+    pre = 0.37
+    model.set_input_statistics(torch.from_numpy(x).to(DEV), pre=pre)
+    y = pre * x.reshape(-1, 28).astype(np.float32).astype(np.float64)
+    mean, std = y.mean(0), y.std(0, ddof=1)
+    assert np.abs(model.in_shift.cpu().numpy() - mean).max() <= 1e-6 * np.abs(y).max()
+    assert np.abs(model.in_scale.cpu().numpy() * std - 1).max() <= 1e-6
+    # packing applies (pre x - shift) * scale before rounding to bf16
+    xb = net.bf16_to_float(model.prepare_input(torch.from_numpy(x).to(DEV), pre=pre)).cpu().numpy()
+    ref = ((pre * x).reshape(-1, 28) - model.in_shift.cpu().numpy()) * model.in_scale.cpu().numpy()
+    assert np.abs(xb.reshape(-1, 32)[:, :28] - ref).max() <= 2 ** -8 * np.abs(ref).max()
+    assert np.all(xb.reshape(-1, 32)[:, 28:] == 0)
 
 
 def test_kappa_and_prediction_shapes():

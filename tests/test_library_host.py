@@ -124,13 +124,17 @@ def test_regulariser_argument_errors_without_device():
     lib = _lib().lib()
     buf = (C.c_float * 64)()
     p = C.cast(buf, C.c_void_p)
-    assert lib.tt_laplacian_reg(None, 2, 2, 2, 1, 1.0, p, p, None, None) == -1
-    assert lib.tt_laplacian_reg(p, 0, 2, 2, 1, 1.0, p, p, None, None) == -2
-    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1, float("nan"), p, p, None, None) == -1
-    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1025, 1.0, p, p, None, None) == -6  # more coefficients than supported
-    assert lib.tt_huber_reg(p, 4, 0.0, 1.0, p, None, None) == -1
-    assert lib.tt_huber_reg(p, -1, 0.1, 1.0, p, None, None) == -2
-    assert lib.tt_huber_reg(None, 0, 0.1, 1.0, None, None, None) == 0
+    d = (C.c_double * 1)()
+    dp = C.cast(d, C.c_void_p)
+    assert lib.tt_laplacian_reg(None, 2, 2, 2, 1, 1.0, p, p, None, None, 0, None) == -1
+    assert lib.tt_laplacian_reg(p, 0, 2, 2, 1, 1.0, p, p, None, None, 0, None) == -2
+    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1, float("nan"), p, p, None, None, 0, None) == -1
+    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1025, 1.0, p, p, None, None, 0, None) == -6  # more coefficients than supported
+    assert lib.tt_laplacian_reg(p, 2, 2, 2, 1, 1.0, p, p, dp, dp, 4095, None) == -1  # partials too short for a value
+    assert lib.tt_huber_reg(p, 4, 0.0, 1.0, p, None, None, 0, None) == -1
+    assert lib.tt_huber_reg(p, -1, 0.1, 1.0, p, None, None, 0, None) == -2
+    assert lib.tt_huber_reg(None, 0, 0.1, 1.0, None, None, None, 0, None) == 0
+    assert lib.tt_huber_reg(p, 4, 0.1, 1.0, p, dp, None, 0, None) == -1  # a value needs partials
     assert lib.tt_gd_step(p, p, None, None, 4, 0.1, 0.0, None) == -1
     assert lib.tt_gd_step(p, p, p, None, 4, float("inf"), 0.0, None) == -1
     assert lib.tt_gd_step(None, None, None, None, 0, 0.1, 0.0, None) == 0
@@ -142,11 +146,12 @@ def test_huber_loss_argument_errors_without_device():
     p = C.cast(buf, C.c_void_p)
     d = (C.c_double * 1)()
     dp = C.cast(d, C.c_void_p)
-    assert lib.tt_huber_loss(p, p, None, 4, 0.0, p, dp, None) == -1
-    assert lib.tt_huber_loss(None, p, None, 4, 0.5, p, dp, None) == -1
-    assert lib.tt_huber_loss(None, None, None, 0, 0.5, None, None, None) == 0
-    assert lib.tt_sumsq(p, 4, 1.0, None, None) == -1
-    assert lib.tt_sumsq(p, -2, 1.0, dp, None) == -2
+    assert lib.tt_huber_loss(p, p, None, 4, 0.0, p, dp, dp, 4096, None) == -1
+    assert lib.tt_huber_loss(None, p, None, 4, 0.5, p, dp, dp, 4096, None) == -1
+    assert lib.tt_huber_loss(None, None, None, 0, 0.5, None, None, None, 0, None) == 0
+    assert lib.tt_sumsq(p, 4, 1.0, None, dp, 4096, None) == -1
+    assert lib.tt_sumsq(p, -2, 1.0, dp, dp, 4096, None) == -2
+    assert lib.tt_sumsq(p, 4, 1.0, dp, None, 0, None) == -1
 
 
 def test_create_rejects_orders_above_twelve_without_device():
