@@ -57,7 +57,8 @@ TILE, OVERLAP, NET_CH = 48, 8, 28
 
 
 def _log(msg, **kw):
-    print(json.dumps({"t": round(time.time(), 3), "msg": msg, **kw}), flush=True)
+    """Progress record (one JSON object per line) on stderr: stdout carries results only."""
+    print(json.dumps({"t": round(time.time(), 3), "msg": msg, **kw}), file=sys.stderr, flush=True)
 
 
 # ---------------------------------------------------------------------------
