@@ -195,6 +195,27 @@ int tt_adjoint(tt_ctx *ctx, const float *y_dev, float *g_dev, float beta, const 
 int tt_loss_grad(tt_ctx *ctx, const float *c_dev, const float *data_dev, const float *w_dev,
                  double mu, double *loss_dev, float *grad_dev, float *resid_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * loss and gradient as tt_loss_grad, with the same arguments and results,
+ * computed by the same kernels, but with its scratch (reduction partials,
+ * folded residual, residual when resid_dev is NULL, the forward batch of
+ * mapped volumes) in an array the library holds on each GPU from the first
+ * tt_create there until the process ends, TT_NOALLOC_SCRATCH_BYTES long.
+ * Needs no workspace (tt_set_workspace is not consulted) and allocates
+ * nothing: no device or pinned memory, no events (timing is not recorded).
+ * The forward batch is the largest that fits beside the other scratch;
+ * TT_ENOMEM if even the smallest does not fit, with the needed size in
+ * tt_last_error() (100^3 voxels at ell_max 8 with 240 projections of
+ * 100x100 pixels x 8 segments fit; 128^3 with 300 projections of 128x128 x
+ * 16 segments do not).
+ * Every call on one GPU uses that GPU's single array and leaves its contents
+ * there: calls that overlap in time on one GPU (other streams, other host
+ * threads, other contexts) race and must be serialised by the caller. */
+#define TT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int tt_loss_grad_noalloc(tt_ctx *ctx, const float *c_dev, const float *data_dev, const float *w_dev,
+                         double mu, double *loss_dev, float *grad_dev, float *resid_dev);
+
 /* ------------------------------------------------------------------------ */
 /* L-BFGS (section 3.5 "Optimization") on the loss above, with history m,    */
 /* initial matrix gamma I (gamma = s^T y / y^T y of the newest pair), and    */

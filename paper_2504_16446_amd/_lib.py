@@ -64,6 +64,7 @@ _SIGS = [
     ("tt_project", C.c_int, [_vp, _fp, _fp]),
     ("tt_adjoint", C.c_int, [_vp, _fp, _fp, C.c_float, _fp]),
     ("tt_loss_grad", C.c_int, [_vp, _fp, _fp, _fp, C.c_double, _dp, _fp, _fp]),
+    ("tt_loss_grad_noalloc", C.c_int, [_vp, _fp, _fp, _fp, C.c_double, _dp, _fp, _fp]),
     ("tt_workspace_bytes", C.c_int64, [_vp, C.c_int]),
     ("tt_set_workspace", C.c_int, [_vp, _vp, C.c_size_t]),
     ("tt_lbfgs_workspace_bytes", C.c_int64, [_vp, C.c_int]),

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtt_hip.so")
-SOURCES = ["tt_api.cpp", "tt_geom.cpp", "tt_proj.hip", "tt_vec.hip", "tt_net.hip", "tt_props.hip", "tt_reg.hip", "tt_stats.hip"]
+SOURCES = ["tt_api.cpp", "tt_geom.cpp", "tt_proj.hip", "tt_vec.hip", "tt_net.hip", "tt_props.hip", "tt_reg.hip", "tt_stats.hip", "tt_static.hip"]
 ARCH = os.environ.get("TT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]

@@ -73,9 +73,9 @@ struct KTimer {
     tt_ctx *c;
     int kind;
     hipEvent_t a = nullptr, b = nullptr;
-    KTimer(tt_ctx *ctx, int k) : c(ctx), kind(k)
+    KTimer(tt_ctx *ctx, int k, bool allowed = true) : c(ctx), kind(k)
     {
-        if (c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+        if (allowed && c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             hipEventRecord(a, c->stream);
     }
     ~KTimer()
@@ -282,6 +282,12 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         delete c;
         return fail(TT_EHIP, "hipGetDevice failed");
     }
+    // device address of the library's static scratch (tt_loss_grad_noalloc),
+    // looked up once per device while it is current
+    if (hipError_t e = static_scratch_init(c->device); e != hipSuccess) {
+        delete c;
+        return fail(TT_EHIP, std::string("static scratch lookup: ") + hipGetErrorString(e));
+    }
     const int S = d.S;
     const int bu_rows = round_up(S * d.Up, 256) + 256;
     std::vector<float> bu((size_t)bu_rows * d.Cp, 0.0f);
@@ -457,6 +463,16 @@ static int need_ws(const tt_ctx *c)
     return TT_OK;
 }
 
+// Scratch of one forward / adjoint / loss evaluation: the attached workspace,
+// or the library's static array (tt_loss_grad_noalloc, untimed: no events).
+struct Scratch {
+    double *part;
+    float *yf, *resid, *M;
+    int pb;
+    bool timed;
+};
+static Scratch attached(const tt_ctx *c) { return {c->d_part, c->d_yf, c->d_resid, c->d_M, c->pb, true}; }
+
 int64_t tt_workspace_bytes(const tt_ctx *c, int forward_batch)
 {
     if (!c) return fail(TT_EINVAL, "ctx is null");
@@ -549,26 +565,31 @@ int tt_basis_matrix(const tt_ctx *c, double *B_host)
     return TT_OK;
 }
 
-static int project_impl(tt_ctx *c, const float *cin, float *I)
+static int project_sc(tt_ctx *c, const Scratch &sc, const float *cin, float *I)
 {
-    if (int rc = need_ws(c)) return rc;
-    for (int s0 = 0; s0 < c->d.S; s0 += c->pb) {
-        const int np = std::min(c->pb, c->d.S - s0);
+    for (int s0 = 0; s0 < c->d.S; s0 += sc.pb) {
+        const int np = std::min(sc.pb, c->d.S - s0);
         hipError_t e;
         {
-            KTimer t(c, TT_K_MAP);
-            e = c->precision == TT_MAP_BF16 ? launch_map_bf16(c->d, cin, c->d_Bsw16, s0, np, c->d_M, c->stream)
-                                            : launch_map_fp32(c->d, cin, c->d_Bsw, s0, np, c->d_M, c->stream);
+            KTimer t(c, TT_K_MAP, sc.timed);
+            e = c->precision == TT_MAP_BF16 ? launch_map_bf16(c->d, cin, c->d_Bsw16, s0, np, sc.M, c->stream)
+                                            : launch_map_fp32(c->d, cin, c->d_Bsw, s0, np, sc.M, c->stream);
         }
         if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
                                          std::string("map: ") + hipGetErrorString(e));
         {
-            KTimer t(c, TT_K_MARCH);
-            e = launch_march(c->d, c->d_frames, c->d_M, s0, np, I, c->stream);
+            KTimer t(c, TT_K_MARCH, sc.timed);
+            e = launch_march(c->d, c->d_frames, sc.M, s0, np, I, c->stream);
         }
         if (e != hipSuccess) return fail(TT_EHIP, std::string("march: ") + hipGetErrorString(e));
     }
     return TT_OK;
+}
+
+static int project_impl(tt_ctx *c, const float *cin, float *I)
+{
+    if (int rc = need_ws(c)) return rc;
+    return project_sc(c, attached(c), cin, I);
 }
 
 int tt_project(tt_ctx *c, const float *cin, float *I)
@@ -577,18 +598,23 @@ int tt_project(tt_ctx *c, const float *cin, float *I)
     return project_impl(c, cin, I);
 }
 
-static int backproject_impl(tt_ctx *c, float *g, float beta, const float *cin, double *partials)
+static int backproject_sc(tt_ctx *c, const Scratch &sc, float *g, float beta, const float *cin, double *partials)
 {
-    if (int rc = need_ws(c)) return rc;
     hipError_t e;
     {
-        KTimer t(c, TT_K_BACKPROJECT);
-        e = launch_backproject(c->d, c->d_frames, c->d_yf, c->d_Bu, c->d_BuT16, c->precision == TT_MAP_BF16, g, beta,
+        KTimer t(c, TT_K_BACKPROJECT, sc.timed);
+        e = launch_backproject(c->d, c->d_frames, sc.yf, c->d_Bu, c->d_BuT16, c->precision == TT_MAP_BF16, g, beta,
                                cin, partials, c->stream);
     }
     if (e != hipSuccess) return fail(e == hipErrorNotSupported ? TT_EUNSUPPORTED : TT_EHIP,
                                      std::string("backproject: ") + hipGetErrorString(e));
     return TT_OK;
+}
+
+static int backproject_impl(tt_ctx *c, float *g, float beta, const float *cin, double *partials)
+{
+    if (int rc = need_ws(c)) return rc;
+    return backproject_sc(c, attached(c), g, beta, cin, partials);
 }
 
 int tt_adjoint(tt_ctx *c, const float *y, float *g, float beta, const float *cin)
@@ -603,26 +629,66 @@ int tt_adjoint(tt_ctx *c, const float *y, float *g, float beta, const float *cin
     return backproject_impl(c, g, beta, beta != 0.0f ? cin : nullptr, nullptr);
 }
 
+static int loss_grad_sc(tt_ctx *c, const Scratch &sc, const float *cin, const float *data, const float *w,
+                        double mu, double *loss, float *grad, float *resid)
+{
+    float *r = resid ? resid : sc.resid;
+    int rc = project_sc(c, sc, cin, r);
+    if (rc) return rc;
+    const int nb = 1024;
+    {
+        KTimer t(c, TT_K_RESIDUAL, sc.timed);
+        TT_HIP(launch_residual_fold(c->d, r, data, w, r, sc.yf, sc.part, nb, c->stream));
+        TT_HIP(launch_sum_partials(sc.part, nb, loss, 1.0, 0, c->stream));
+    }
+    double *p2 = sc.part + nb;
+    rc = backproject_sc(c, sc, grad, (float)(2.0 * mu), cin, p2);
+    if (rc) return rc;
+    TT_HIP(launch_sum_partials(p2, backproject_blocks(c->d), loss, mu, 1, c->stream));
+    return TT_OK;
+}
+
 int tt_loss_grad(tt_ctx *c, const float *cin, const float *data, const float *w, double mu, double *loss,
                  float *grad, float *resid)
 {
     if (!c || !cin || !data || !loss || !grad) return fail(TT_EINVAL, "null pointer");
     if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(TT_EINVAL, "mu must be finite and >= 0");
     if (int rc = need_ws(c)) return rc;
-    float *r = resid ? resid : c->d_resid;
-    int rc = project_impl(c, cin, r);
-    if (rc) return rc;
-    const int nb = 1024;
-    {
-        KTimer t(c, TT_K_RESIDUAL);
-        TT_HIP(launch_residual_fold(c->d, r, data, w, r, c->d_yf, c->d_part, nb, c->stream));
-        TT_HIP(launch_sum_partials(c->d_part, nb, loss, 1.0, 0, c->stream));
+    return loss_grad_sc(c, attached(c), cin, data, w, mu, loss, grad, resid);
+}
+
+int tt_loss_grad_noalloc(tt_ctx *c, const float *cin, const float *data, const float *w, double mu, double *loss,
+                         float *grad, float *resid)
+{
+    if (!c || !cin || !data || !loss || !grad) return fail(TT_EINVAL, "null pointer");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(TT_EINVAL, "mu must be finite and >= 0");
+    char *base = static_cast<char *>(static_scratch(c->device));
+    if (!base) return fail(TT_EHIP, "the library's static scratch is not available on device " +
+                                        std::to_string(c->device));
+    // same layout as an attached workspace, the batch as large as the array allows
+    WsLayout L = ws_layout(c, 0);
+    if (resid) {  // the residual goes to the caller's buffer: no data-sized scratch
+        L.M = L.resid;
+        L.total = L.resid;
     }
-    double *p2 = c->d_part + nb;
-    rc = backproject_impl(c, grad, (float)(2.0 * mu), cin, p2);
-    if (rc) return rc;
-    TT_HIP(launch_sum_partials(p2, backproject_blocks(c->d), loss, mu, 1, c->stream));
-    return TT_OK;
+    const size_t cap = kStaticScratchBytes;
+    const long long fit = cap > L.total ? (long long)((cap - L.total) / c->per_proj) : 0;
+    const int pb = batch_round_down(c, fit);
+    if (pb < batch_min(c))
+        return fail(TT_ENOMEM, "problem needs " + std::to_string(L.total + c->per_proj * (size_t)batch_min(c)) +
+                                   " bytes of scratch, above the static limit of " + std::to_string(cap) +
+                                   " bytes; use tt_loss_grad with a workspace");
+    Scratch sc;
+    sc.part = reinterpret_cast<double *>(base + L.part);
+    sc.yf = reinterpret_cast<float *>(base + L.yf);
+    sc.resid = resid ? nullptr : reinterpret_cast<float *>(base + L.resid);
+    sc.M = reinterpret_cast<float *>(base + L.M);
+    sc.pb = pb;
+    sc.timed = false;
+    // the map writes interior voxels only; the array holds whatever the last
+    // call on this device left there, so the zero border is restored each time
+    TT_HIP(launch_zero(sc.M, c->per_proj * (size_t)pb, c->stream));
+    return loss_grad_sc(c, sc, cin, data, w, mu, loss, grad, resid);
 }
 
 // ---------------------------------------------------------------------------

@@ -148,6 +148,16 @@ size_t chstats_work_doubles();
 hipError_t launch_channel_stats(const float *x, long long nvox, int cstride, int nch, float pre, float *shift,
                                 float *scale, double *work, hipStream_t st);
 
+// Library-owned scratch of the allocation-free loss/gradient entry point
+// (tt_static.hip): a fixed array per device, looked up once per device.
+constexpr size_t kStaticScratchBytes = TT_NOALLOC_SCRATCH_BYTES;
+// Looks up this device's scratch address (once; `device` must be current).
+hipError_t static_scratch_init(int device);
+// Device address of the scratch on `device` (null before a successful init).
+void *static_scratch(int device);
+// p[0 .. bytes) = 0 with a fill kernel (bytes and p 16-byte aligned).
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
 // Reductions: out[slot] = scale * sum of partials[0..n).
 hipError_t launch_sum_partials(const double *partials, int n, double *out, double scale,
                                int accumulate, hipStream_t st);

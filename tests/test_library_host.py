@@ -82,6 +82,7 @@ def test_error_codes_without_device():
     assert lib.tt_project(None, None, None) == -1
     assert lib.tt_adjoint(None, None, None, C.c_float(0), None) == -1
     assert lib.tt_lbfgs_step(None) == -1
+    assert lib.tt_loss_grad_noalloc(None, None, None, None, C.c_double(0.0), None, None, None) == -1
     assert lib.tt_error_string(-5) == b"non-finite value"
 
 
