@@ -107,7 +107,10 @@ typedef struct tt_ctx tt_ctx;
  * float64 on the host and uploads them as device tables (the only device
  * memory the library allocates).  Device computations need a workspace
  * (tt_set_workspace) first.  Synchronous.  On failure *out is NULL. */
-int tt_create(const tt_geometry *geom, tt_ctx **out);  /* TT_EUNSUPPORTED for ell_max > 12 */
+/* TT_EUNSUPPORTED for ell_max > 12, more than 16 distinct segments, or a
+ * projection image of 2^24 or more float4 groups (nj nk ceil(U/4) with U the
+ * distinct segments rounded up to 4, 8 or 16). */
+int tt_create(const tt_geometry *geom, tt_ctx **out);
 /* Waits for the context's stream, then frees its tables and buffers. */
 void tt_destroy(tt_ctx *ctx);
 

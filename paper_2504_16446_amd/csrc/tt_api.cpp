@@ -261,6 +261,12 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     d.S = g.n_proj; d.nj = g.nj; d.nk = g.nk; d.nseg = g.n_seg;
     d.step = (float)g.step;
     d.joseph = 0;
+    // the sample lattice of every projection is symmetric under x -> -x when
+    // the detector is centred (no offsets); with even nx the lower and upper
+    // x-halves then pair voxel by voxel
+    bool centred = true;
+    for (int s = 0; s < g.n_proj; ++s) centred = centred && g.joff[s] == 0.0 && g.koff[s] == 0.0;
+    d.inv_pair = centred && g.nx % 2 == 0 ? 1 : 0;
     // Even orders: Y(-q) = Y(q) (and the Gaussian kernels are symmetric too), and
     // with segments over the full circle segment c + n_seg/2 probes exactly the
     // antipodes of segment c.
@@ -274,6 +280,11 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         return fail(TT_EUNSUPPORTED, "more than 16 distinct segments");
     }
     d.Up = d.U <= 4 ? 4 : (d.U <= 8 ? 8 : 16);
+    if ((long long)d.nj * d.nk * (d.Up / 4) >= (1LL << 24)) {  // the adjoint's 24-bit row offsets
+        delete c;
+        return fail(TT_EUNSUPPORTED, "detector too large: nj * nk * " + std::to_string(d.Up / 4) +
+                                         " must stay below 2^24 (float4 units of one projection)");
+    }
     // staged march LDS per 256-ray tile: 32 KiB for four unique segments, 64
     // KiB for more (measured best of 32/48/64 KiB on 100^3 x 4 and 256^3 x 8)
     d.march_lds = plan_slabs(c->frames, d.Up, (d.Up == 4 ? 32 : 64) * 1024);
@@ -315,7 +326,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         for (int ks = 0; ks < KS; ++ks)
             for (int l = 0; l < 64; ++l)
                 bsw[((size_t)rt * KS + ks) * 64 + l] = bu[((size_t)rt * 16 + l % 16) * d.Cp + 4 * ks + l / 16];
-    c->n_part = 1024 + std::max(4096, backproject_blocks(d));
+    c->n_part = 1024 + std::max(4096, backproject_blocks_max(d));
 
     auto cleanup = [&](int code, const std::string &msg) {
         tt_destroy(c);

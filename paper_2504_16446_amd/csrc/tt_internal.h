@@ -86,6 +86,9 @@ struct Dims {
     float step;         // sample spacing of the trilinear model (1 for Joseph: no step factor)
     int march_lds;      // dynamic LDS bytes of the staged march (0: no projection staged)
     int joseph;         // 0: unit-step trilinear samples, 1: Joseph's method
+    int inv_pair;       // 1: point-inversion-symmetric geometry (no detector offsets, even nx):
+                        //    the trilinear adjoint with four unique segments enumerates each
+                        //    voxel pair (v, -v) once
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
@@ -109,7 +112,10 @@ hipError_t launch_residual_fold(const Dims &d, const float *Ip, const float *dat
 hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const float *yf,
                               const float *Bu, const uint16_t *BuT16, int bf16, float *g, float beta,
                               const float *c, double *partials, hipStream_t st);
+// Blocks (= float64 partials) of the adjoint launch; the largest over the
+// adjoint variants of a geometry.
 int backproject_blocks(const Dims &d);
+int backproject_blocks_max(const Dims &d);
 
 // Derived per-voxel quantities: out[v][kPropFields] from c[v][C] (tt_props.hip).
 constexpr int kPropFields = 22;

@@ -1098,7 +1098,247 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
     }
 }
 
-int backproject_blocks(const Dims &d) { return ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
+
+// ---------------------------------------------------------------------------
+// backproject, paired by point inversion (trilinear model, no detector
+// offsets, even nx, four unique segments).  The sample lattice of a projection,
+// o + j e_j + k e_k + n step d with o = -((nj-1)/2 e_j + (nk-1)/2 e_k), is
+// symmetric under x -> -x with (j, k, n) -> (nj-1-j, nk-1-k, -n); the voxel
+// grid and the tent are symmetric too.  So the weight of ray (j, k) at voxel
+// v equals the weight of ray (nj-1-j, nk-1-k) at the inverted voxel
+// v' = (nx-1-ix, ny-1-iy, nz-1-iz), and one enumeration of v's rays and
+// samples gives Q_s(v) and Q_s(v') (the second from the mirrored residual
+// rows).  Block: waves 0, 1 own x-slices 2 bx + w of the lower half
+// (ix < nx / 2) over an 8 x 8 (y, z) tile; waves 2, 3 own the inverses of
+// waves 0, 1's voxels lane by lane.  Per pair of projections (s, s + 1) the
+// lower waves enumerate s and the upper waves s + 1; each hands the
+// partner's Q through LDS, and each wave then contracts both projections'
+// Q with B^T on MFMA into its own accumulators.  Enumeration work per voxel
+// and projection is halved; the transpose maps are unchanged.
+// ---------------------------------------------------------------------------
+template <int UP, int MT, bool BF16>
+__global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict__ yf,
+                                                         const ProjFrame *__restrict__ frames,
+                                                         const float *__restrict__ Bu, const s4 *__restrict__ BuT16,
+                                                         int S, int nx, int ny, int nz, int nj, int nk, int C, int Cp,
+                                                         float step, float *__restrict__ g, float beta,
+                                                         const float *__restrict__ c, double *__restrict__ partials)
+{
+    constexpr int QS = 64 * (UP + 1);
+    __shared__ float Qs[4][QS];      // each wave's own Q (wave-private)
+    __shared__ float Qx[2][4][QS];   // Q handed over by the partner wave, double-buffered
+    __shared__ double ws[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave-uniform (scalar) wave index: the projection each wave enumerates, and
+    // hence its frame loads, stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool upper = wave >= 2;
+    const int nxh = nx >> 1;
+    const int nbx = (nxh + 1) / 2, nby = (ny + 7) / 8;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+    // the lower-half voxel of this lane's pair, and this wave's own voxel
+    const int px = bx * 2 + (wave & 1), py = by * 8 + (lane >> 3), pz = bz * 8 + (lane & 7);
+    const bool valid = px < nxh && py < ny && pz < nz;
+    const int ix = upper ? nx - 1 - px : px, iy = upper ? ny - 1 - py : py, iz = upper ? nz - 1 - pz : pz;
+    const double xv[3] = {ix - 0.5 * (nx - 1), iy - 0.5 * (ny - 1), iz - 0.5 * (nz - 1)};
+    const double inv_step = 1.0 / (double)step;
+    const float stepf = step, inv_stepf = (float)inv_step;
+
+    f4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // B_s^T operands of one projection in MFMA lane order (loaded at the top of
+    // an iteration, so that the enumeration hides their latency)
+    struct BOps {
+        s4 b16[BF16 ? MT : 1];
+        float f[BF16 ? 1 : UP / 4][MT];
+    };
+    auto load_ops = [&](int s, BOps &o) {
+        if constexpr (BF16) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                o.b16[mt] = BuT16[((long long)s * Cp + mt * 16 + (lane & 15)) * 4 + (lane >> 4)];
+        } else {
+            const float *Bs = Bu + (long long)s * UP * Cp;
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o.f[ks][mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+        }
+    };
+    // g tile += B_s^T (coefficients x u) * Q^T (u x voxels), Q from the LDS tile Qt
+    auto contract = [&](const BOps &o, const float *Qt) {
+        if constexpr (BF16) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float *qv = Qt + (nt * 16 + (lane & 15)) * (UP + 1);
+                const int u0 = 4 * (lane >> 4);
+                s4 bv;
+                bv.x = u0 + 0 < UP ? f2bf(qv[min(u0 + 0, UP - 1)]) : (short)0;
+                bv.y = u0 + 1 < UP ? f2bf(qv[min(u0 + 1, UP - 1)]) : (short)0;
+                bv.z = u0 + 2 < UP ? f2bf(qv[min(u0 + 2, UP - 1)]) : (short)0;
+                bv.w = u0 + 3 < UP ? f2bf(qv[min(u0 + 3, UP - 1)]) : (short)0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x16bf16(o.b16[mt], bv, acc[mt][nt]);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks) {
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const float bv = qw_at<UP>(Qt, nt, ks, lane);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(o.f[ks][mt], bv, acc[mt][nt]);
+                }
+            }
+        }
+    };
+
+    int buf = 0;
+    for (int s0 = 0; s0 < S; s0 += 2) {
+        const int s_own = s0 + (upper ? 1 : 0), s_oth = s0 + (upper ? 0 : 1);
+        const bool has_own = s_own < S, has_oth = s_oth < S;
+        BOps ops_own, ops_oth;
+        load_ops(has_own ? s_own : s0, ops_own);
+        load_ops(has_oth ? s_oth : s0, ops_oth);
+        float q[UP], qm[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) q[u] = qm[u] = 0.0f;
+        if (has_own && valid) {
+            const ProjFrame &f = frames[s_own];
+            // voxel centre in the ray frame (float64), split into integer + fraction
+            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+            const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
+            const double af = floor(a), bf = floor(bb), tf = floor(ts);
+            const int ai = (int)af, bi = (int)bf;
+            const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
+            const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
+            float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
+            asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
+            const float ljf = (float)f.lj;
+            const int jlo = max(0, ai + (int)ceilf(ar - ljf));
+            const int jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
+            const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
+            const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
+            const f4 *ys = reinterpret_cast<const f4 *>(yf + (long long)s_own * nj * nk * UP);
+            for (int j = jlo; j <= jhi; ++j) {
+                const float dj = (float)(j - ai) - ar;
+                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
+                                         fmaf(f.hull[4], dj, cu[2]));
+                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
+                                         fmaf(f.hull[10], dj, cl[2]));
+                const int klo = max(0, bi + (int)ceilf(zmin));
+                const int khi = min(nk - 1, bi + (int)floorf(zmax));
+                const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
+                const f4 *yrow = ys + __umul24(j, nk * (UP / 4));
+                // mirrored ray (nj-1-j, nk-1-k): row nj-1-j read backwards from column nk-1
+                const f4 *yrowm = ys + __umul24(nj - 1 - j, nk * (UP / 4)) + (nk - 1) * (UP / 4);
+                float dk = (float)(klo - bi) - br;
+                for (int k = klo; k <= khi; ++k, dk += 1.0f) {
+                    f4 yv[UP / 4], ym[UP / 4];
+#pragma unroll
+                    for (int u4 = 0; u4 < UP / 4; ++u4) {
+                        yv[u4] = yrow[k * (UP / 4) + u4];
+                        ym[u4] = yrowm[u4 - k * (UP / 4)];
+                    }
+                    const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
+                    float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+#pragma unroll
+                    for (int m = 1; m < 3; ++m) {
+                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
+                        thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                    }
+                    float wsum = 0.0f;
+                    const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
+                    const float tend = (m1 - tr + 0.5f) * stepf;
+                    for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
+                        const float wx = 1.0f - fabsf(fmaf(tau, f.df[0], P[0]));
+                        const float wy = 1.0f - fabsf(fmaf(tau, f.df[1], P[1]));
+                        const float wz = 1.0f - fabsf(fmaf(tau, f.df[2], P[2]));
+                        wsum = fmaf(wx * wy, wz, wsum);
+                    }
+#pragma unroll
+                    for (int u4 = 0; u4 < UP; u4 += 4) {
+                        q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
+                        q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
+                        q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
+                        q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
+                        qm[u4 + 0] = fmaf(wsum, ym[u4 / 4].x, qm[u4 + 0]);
+                        qm[u4 + 1] = fmaf(wsum, ym[u4 / 4].y, qm[u4 + 1]);
+                        qm[u4 + 2] = fmaf(wsum, ym[u4 / 4].z, qm[u4 + 2]);
+                        qm[u4 + 3] = fmaf(wsum, ym[u4 / 4].w, qm[u4 + 3]);
+                    }
+                }
+            }
+        }
+        float *Qown = Qs[wave];
+        float *Qout = Qx[buf][wave ^ 2];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            Qown[lane * (UP + 1) + u] = q[u];
+            Qout[lane * (UP + 1) + u] = qm[u];
+        }
+        // the partner's tile is complete; the tile of the other buffer was last
+        // read before this barrier's predecessor, so one barrier per pair suffices
+        __syncthreads();
+        if (has_own) contract(ops_own, Qown);
+        if (has_oth) contract(ops_oth, Qx[buf][wave]);
+        buf ^= 1;
+    }
+
+    // epilogue: lane holds rows (coefficients) 16 mt + 4 (lane/16) + r of voxel column 16 nt + lane % 16
+    double c2 = 0.0;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int lv = nt * 16 + (lane & 15);
+        const int qy = by * 8 + (lv >> 3), qz = bz * 8 + (lv & 7);
+        if (px < nxh && qy < ny && qz < nz) {
+            const int vx = ix, vy = upper ? ny - 1 - qy : qy, vz = upper ? nz - 1 - qz : qz;
+            const long long base = (((long long)vx * ny + vy) * nz + vz) * C;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mt * 16 + 4 * (lane >> 4) + r;
+                    if (i < C) {
+                        float val = acc[mt][nt][r];
+                        if (c) {
+                            float cv = c[base + i];
+                            val += beta * cv;
+                            c2 += (double)cv * (double)cv;
+                        }
+                        g[base + i] = val;
+                    }
+                }
+            }
+        }
+    }
+    if (partials) {
+        double tot = block_sum(c2, ws);
+        if (tid == 0) partials[bid] = tot;
+    }
+}
+
+// Pairing pays with four unique segments (C2-like workloads: the adjoint
+// 4.21 -> 3.21 ms at 100^3 / 240 projections).  With eight, its own and
+// mirrored residual loads and accumulators raise the register count from 78
+// to 102 (three waves per SIMD instead of four) and the kernel, then bound by
+// load latency rather than by VALU issue, measured 10% slower than the
+// unpaired one (5% of it the per-pair barrier), so it is not used there.
+static bool use_inv_pair(const Dims &d) { return d.inv_pair && !d.joseph && d.Up == 4; }
+static int backproject_inv_blocks(const Dims &d) { return ((d.nx / 2 + 1) / 2) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
+
+int backproject_blocks(const Dims &d)
+{
+    return use_inv_pair(d) ? backproject_inv_blocks(d) : ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
+}
+int backproject_blocks_max(const Dims &d) { return ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
 
 template <int UP, int MT>
 static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, const float *Bu, const uint16_t *BuT16,
@@ -1106,6 +1346,17 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
 {
     const s4 *bt = reinterpret_cast<const s4 *>(BuT16);
     const dim3 grid(backproject_blocks(d)), block(256);
+    if constexpr (UP == 4) {
+        if (use_inv_pair(d)) {
+            if (bf16)
+                hipLaunchKernelGGL((k_backproject_inv<UP, MT, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
+                                   d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            else
+                hipLaunchKernelGGL((k_backproject_inv<UP, MT, false>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
+                                   d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            return hipGetLastError();
+        }
+    }
     if (bf16 && d.joseph)
         hipLaunchKernelGGL((k_backproject<UP, MT, true, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S, d.nx,
                            d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);

@@ -52,6 +52,12 @@ CASES = {
     "steep_tilts": lambda: steep(),          # forward march gathers these rays from global memory
     "degenerate": lambda: degenerate(),      # 1-voxel-thick volume, one detector row, 2 segments
     "c1": lambda: workload("c1"),
+    # the adjoint pairs each voxel with its point inverse (centred detector, even
+    # nx, four unique segments): an odd projection count leaves the last pair
+    # half empty, and nx / 2 odd leaves the last block with one x-slice pair
+    # outside the volume
+    "odd_projection_count": lambda: small(ell_max=4, n_rot=5),
+    "paired_l8_ragged": lambda: small(ell_max=8, n=(18, 13, 11), n_rot=3),
 }
 
 

@@ -5,11 +5,14 @@ segment values Q_s and B rounded to bf16).
 Parity: against the float64 oracle evaluated with the same rounding points.
 Forward: relative L2 <= 1e-5 (both sides round the same float32 inputs c and
 B; products of two bf16 values are exact in fp32, so only fp32 accumulation
-separates them).  Adjoint: relative L2 <= 2e-5, because its rounding point Q
-is an intermediate: a value within an fp32 rounding (~1e-7 relative) of a
-bf16 rounding boundary rounds the other way with probability p ~ 2^-23 / 2^-8
-~ 3e-5, which moves that element by one bf16 unit (2^-8 relative); such flips
-add incoherently, giving ~sqrt(p) 2^-8 ~ 2e-5 relative L2 in the worst case.
+separates them).  Adjoint: relative L2 <= 5e-5, because its rounding point Q
+is an intermediate summed in fp32 over ~16 weighted residual terms per voxel
+and projection: its error of ~sqrt(16) 2^-24 ~ 2.4e-7 relative makes a value
+that close to a bf16 rounding boundary round the other way, with probability
+p ~ 2 x 2.4e-7 / 2^-8 ~ 1.2e-4 per element, moving it by one bf16 unit (2^-8
+relative); such flips add incoherently, giving ~sqrt(p) 2^-8 ~ 4e-5 relative
+L2.  (Which Q values flip depends on the fp32 summation order, so no oracle
+evaluated in float64 can take the same rounding decisions.)
 The error against the unrounded float64 oracle is reported and bounded by the
 bf16 unit roundoff scale (<= 1e-2).
 """
@@ -66,5 +69,5 @@ def test_bf16_adjoint(name):
     got = P.adjoint(_t(y)).cpu().numpy()
     e_r, e = rel_l2(got, ref_rounded), rel_l2(got, ref)
     print(f"{name} bf16 adjoint: vs rounded oracle {e_r:.2e}, vs float64 oracle {e:.2e}")
-    assert e_r <= 2e-5
+    assert e_r <= 5e-5
     assert e <= 1e-2
