@@ -105,6 +105,23 @@ def _traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def _compute_counters(kernel, workload):
+    """Issue-side counters per launch of one kernel class (VALU busy, active
+    lanes per VALU instruction, MFMA busy) from committed rocprofv3 runs, if current."""
+    path = os.path.join(ROOT, "profiles", f"pmc_compute_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != _source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    return {"valu_busy": k["valu_busy"], "active_lanes": k["active_lanes"], "mfma_busy": k["mfma_busy"],
+            "source": f"profiles/pmc_compute_{workload}.json"}
+
+
 def cpu_sample_index(w, n_sample):
     import numpy as np
     return np.linspace(0, w.n_proj - 1, n_sample).round().astype(int)
@@ -423,6 +440,7 @@ def main():
             r["frac"] = r["achieved"] / r["peak"]
             r["avg_launch_ms"] = kernels[k]["avg_launch_ms"]
             r["traffic"] = _traffic(k, w.name)
+            r["counters"] = _compute_counters(k, w.name)
             roofs[k] = r
     dom = max(roofs, key=lambda k: kernels[k]["ms_per_step"])
     roofline = dict(kernel=dom, **roofs[dom])
