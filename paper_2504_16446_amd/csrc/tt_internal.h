@@ -89,6 +89,8 @@ struct Dims {
     int inv_pair;       // 1: point-inversion-symmetric geometry (no detector offsets, even nx):
                         //    the trilinear adjoint with four unique segments enumerates each
                         //    voxel pair (v, -v) once
+    int win_ok;         // 1: every projection's residual window of a 4 x 8 x 8 brick fits the
+                        //    adjoint's LDS window (trilinear model, eight unique segments)
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
@@ -116,6 +118,7 @@ hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const floa
 // adjoint variants of a geometry.
 int backproject_blocks(const Dims &d);
 int backproject_blocks_max(const Dims &d);
+bool backproject_window_fits(const std::vector<ProjFrame> &frames);
 
 // Derived per-voxel quantities: out[v][kPropFields] from c[v][C] (tt_props.hip).
 constexpr int kPropFields = 22;

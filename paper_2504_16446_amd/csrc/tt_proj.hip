@@ -1221,6 +1221,10 @@ __global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict
             const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
             float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
             asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
+            // the sample step in vector registers: reloading it from the frame per
+            // ray (scalar pressure) made each ray wait on the scalar load
+            float dfv[3] = {f.df[0], f.df[1], f.df[2]};
+            asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
             const float ljf = (float)f.lj;
             const int jlo = max(0, ai + (int)ceilf(ar - ljf));
             const int jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
@@ -1258,9 +1262,9 @@ __global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict
                     const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
                     const float tend = (m1 - tr + 0.5f) * stepf;
                     for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
-                        const float wx = 1.0f - fabsf(fmaf(tau, f.df[0], P[0]));
-                        const float wy = 1.0f - fabsf(fmaf(tau, f.df[1], P[1]));
-                        const float wz = 1.0f - fabsf(fmaf(tau, f.df[2], P[2]));
+                        const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
+                        const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
+                        const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
                         wsum = fmaf(wx * wy, wz, wsum);
                     }
 #pragma unroll
@@ -1325,6 +1329,268 @@ __global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// backproject with the residual window staged in LDS (trilinear model).  Each
+// block's 4 x 8 x 8 voxel brick reads, per projection, only the residual rays
+// of a small detector window (its shadow widened by the cube's L1 reach); the
+// window is copied from HBM into LDS by the direct global-to-LDS loads of
+// gfx950 one projection ahead (into the other of two buffers), so that the
+// per-ray residual reads of the enumeration are LDS reads instead of
+// scattered L2 / HBM loads.  One block barrier per projection (the four
+// waves process neighbouring x-slices of the same projection).
+// ---------------------------------------------------------------------------
+constexpr int kWinMax = 22;  // window rows and columns (the host checks every projection)
+
+template <int UP, int MT, bool BF16>
+__global__ __launch_bounds__(256) void k_backproject_win(const float *__restrict__ yf,
+                                                         const ProjFrame *__restrict__ frames,
+                                                         const float *__restrict__ Bu, const s4 *__restrict__ BuT16,
+                                                         int S, int nx, int ny, int nz, int nj, int nk, int C, int Cp,
+                                                         float step, float *__restrict__ g, float beta,
+                                                         const float *__restrict__ c, double *__restrict__ partials)
+{
+    constexpr int Q = UP / 4;                 // float4 per ray
+    constexpr int WROW = kWinMax * Q;         // float4 per window row
+    __shared__ f4 winA[kWinMax * WROW];
+    __shared__ f4 winB[kWinMax * WROW];
+    __shared__ float Qs[4][64 * (UP + 1)];
+    __shared__ double ws[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nbx = (nx + 3) / 4, nby = (ny + 7) / 8;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+    const int ix = bx * 4 + wave, iy = by * 8 + (lane >> 3), iz = bz * 8 + (lane & 7);
+    const bool valid = ix < nx && iy < ny && iz < nz;
+    const double xv[3] = {ix - 0.5 * (nx - 1), iy - 0.5 * (ny - 1), iz - 0.5 * (nz - 1)};
+    const double inv_step = 1.0 / (double)step;
+    const float stepf = step, inv_stepf = (float)inv_step;
+
+    // detector window of projection s: rows and columns every voxel of the
+    // brick can reach (its L1 reach lj, lk around its detector position, one
+    // more on each side for rounding), clipped to the detector
+    auto window = [&](int s, int &j0, int &k0, int &nr, int &nc) {
+        const ProjFrame &f = frames[s];
+        // the brick's voxel-centre box (clipped to the volume), centred coordinates
+        const double lo3[3] = {bx * 4 - 0.5 * (nx - 1), by * 8 - 0.5 * (ny - 1), bz * 8 - 0.5 * (nz - 1)};
+        const double hi3[3] = {min(nx, bx * 4 + 4) - 1 - 0.5 * (nx - 1), min(ny, by * 8 + 8) - 1 - 0.5 * (ny - 1),
+                               min(nz, bz * 8 + 8) - 1 - 0.5 * (nz - 1)};
+        double amin = 0.0, amax = 0.0, bmin = 0.0, bmax = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double ea = f.ej[a], ka = f.ek[a];
+            amin += (ea >= 0.0 ? lo3[a] - f.o[a] : hi3[a] - f.o[a]) * ea;
+            amax += (ea >= 0.0 ? hi3[a] - f.o[a] : lo3[a] - f.o[a]) * ea;
+            bmin += (ka >= 0.0 ? lo3[a] - f.o[a] : hi3[a] - f.o[a]) * ka;
+            bmax += (ka >= 0.0 ? hi3[a] - f.o[a] : lo3[a] - f.o[a]) * ka;
+        }
+        const int ja = max(0, (int)ceil(amin - f.lj) - 1), jb = min(nj - 1, (int)floor(amax + f.lj) + 1);
+        const int ka0 = max(0, (int)ceil(bmin - f.lk) - 1), kb = min(nk - 1, (int)floor(bmax + f.lk) + 1);
+        j0 = __builtin_amdgcn_readfirstlane(ja);
+        k0 = __builtin_amdgcn_readfirstlane(ka0);
+        nr = __builtin_amdgcn_readfirstlane(max(0, min(kWinMax, jb - ja + 1)));
+        nc = __builtin_amdgcn_readfirstlane(max(0, min(kWinMax, kb - ka0 + 1)));
+    };
+    // asynchronous copy of projection s's window into win (rows spread over the waves)
+    auto stage = [&](int s, f4 *win, int j0, int k0, int nr, int nc) {
+        const f4 *src = reinterpret_cast<const f4 *>(yf) + (((long long)s * nj + j0) * nk + k0) * Q;
+        const int rowf4 = nc * Q;
+        for (int r = wave; r < nr; r += 4) {
+#pragma unroll
+            for (int l0 = 0; l0 < WROW; l0 += 64) {
+                if (l0 + lane < rowf4)
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(src + (long long)r * nk * Q + l0 + lane),
+                        (__attribute__((address_space(3))) void *)(win + r * WROW + l0), 16, 0, 0);
+            }
+        }
+    };
+
+    f4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    float *Qw = Qs[wave];
+
+    // projection s: enumerate from the staged window, then contract on MFMA
+    auto body = [&](int s, const f4 *win, int wj0, int wk0, int wnr, int wnc) {
+        const ProjFrame &f = frames[s];
+        s4 avb[MT];
+        float avf[UP / 4][MT];
+        if constexpr (BF16) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                avb[mt] = BuT16[((long long)s * Cp + mt * 16 + (lane & 15)) * 4 + (lane >> 4)];
+        } else {
+            const float *Bs = Bu + (long long)s * UP * Cp;
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) avf[ks][mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+        }
+        float q[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) q[u] = 0.0f;
+        if (valid) {
+            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+            const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
+            const double af = floor(a), bf = floor(bb), tf = floor(ts);
+            const int ai = (int)af, bi = (int)bf;
+            const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
+            const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
+            float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
+            asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
+            // the sample step in vector registers: reloading it from the frame per
+            // ray (scalar pressure) made each ray wait on the scalar load
+            float dfv[3] = {f.df[0], f.df[1], f.df[2]};
+            asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
+            const float ljf = (float)f.lj;
+            // rows and columns stay inside the staged window (it contains every ray
+            // the voxel can reach; the clamps only guard the LDS indices)
+            const int jlo = max(wj0, ai + (int)ceilf(ar - ljf));
+            const int jhi = min(wj0 + wnr - 1, ai + (int)floorf(ar + ljf));
+            const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
+            const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
+            for (int j = jlo; j <= jhi; ++j) {
+                const float dj = (float)(j - ai) - ar;
+                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
+                                         fmaf(f.hull[4], dj, cu[2]));
+                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
+                                         fmaf(f.hull[10], dj, cl[2]));
+                const int klo = max(wk0, bi + (int)ceilf(zmin));
+                const int khi = min(wk0 + wnc - 1, bi + (int)floorf(zmax));
+                const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
+                const f4 *wrow = win + (j - wj0) * WROW - wk0 * Q;
+                float dk = (float)(klo - bi) - br;
+                for (int k = klo; k <= khi; ++k, dk += 1.0f) {
+                    f4 yv[Q];
+#pragma unroll
+                    for (int u4 = 0; u4 < Q; ++u4) yv[u4] = wrow[k * Q + u4];
+                    const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
+                    float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+#pragma unroll
+                    for (int m = 1; m < 3; ++m) {
+                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
+                        thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                    }
+                    float wsum = 0.0f;
+                    const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
+                    const float tend = (m1 - tr + 0.5f) * stepf;
+                    for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
+                        const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
+                        const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
+                        const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
+                        wsum = fmaf(wx * wy, wz, wsum);
+                    }
+#pragma unroll
+                    for (int u4 = 0; u4 < UP; u4 += 4) {
+                        q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
+                        q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
+                        q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
+                        q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UP; ++u) Qw[lane * (UP + 1) + u] = q[u];
+        __builtin_amdgcn_wave_barrier();
+        if constexpr (BF16) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float *qv = Qw + (nt * 16 + (lane & 15)) * (UP + 1);
+                const int u0 = 4 * (lane >> 4);
+                s4 bv;
+                bv.x = u0 + 0 < UP ? f2bf(qv[min(u0 + 0, UP - 1)]) : (short)0;
+                bv.y = u0 + 1 < UP ? f2bf(qv[min(u0 + 1, UP - 1)]) : (short)0;
+                bv.z = u0 + 2 < UP ? f2bf(qv[min(u0 + 2, UP - 1)]) : (short)0;
+                bv.w = u0 + 3 < UP ? f2bf(qv[min(u0 + 3, UP - 1)]) : (short)0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x16bf16(avb[mt], bv, acc[mt][nt]);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks) {
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const float bv = qw_at<UP>(Qw, nt, ks, lane);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(avf[ks][mt], bv, acc[mt][nt]);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    // two buffers: projection s reads one while the copy of projection s + 1
+    // fills the other
+    int cj0, ck0, cnr, cnc;
+    window(0, cj0, ck0, cnr, cnc);
+    stage(0, winA, cj0, ck0, cnr, cnc);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int s = 0; s < S; ++s) {
+        f4 *cur = (s & 1) ? winB : winA;
+        f4 *nxt = (s & 1) ? winA : winB;
+        int nj0 = 0, nk0 = 0, nnr = 0, nnc = 0;
+        if (s + 1 < S) {
+            window(s + 1, nj0, nk0, nnr, nnc);
+            stage(s + 1, nxt, nj0, nk0, nnr, nnc);
+        }
+        body(s, cur, cj0, ck0, cnr, cnc);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        cj0 = nj0; ck0 = nk0; cnr = nnr; cnc = nnc;
+    }
+
+    // epilogue: lane holds rows (coefficients) 16 mt + 4 (lane/16) + r of voxel column 16 nt + lane % 16
+    double c2 = 0.0;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int lv = nt * 16 + (lane & 15);
+        const int vy = by * 8 + (lv >> 3), vz = bz * 8 + (lv & 7);
+        if (ix < nx && vy < ny && vz < nz) {
+            const long long base = (((long long)ix * ny + vy) * nz + vz) * C;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mt * 16 + 4 * (lane >> 4) + r;
+                    if (i < C) {
+                        float val = acc[mt][nt][r];
+                        if (c) {
+                            float cv = c[base + i];
+                            val += beta * cv;
+                            c2 += (double)cv * (double)cv;
+                        }
+                        g[base + i] = val;
+                    }
+                }
+            }
+        }
+    }
+    if (partials) {
+        double tot = block_sum(c2, ws);
+        if (tid == 0) partials[bid] = tot;
+    }
+}
+
+// Largest detector window of a 4 x 8 x 8 brick over the projections: rows
+// <= 3|e_jx| + 7|e_jy| + 7|e_jz| + 2 l_j + 3 (the voxel-centre span, the L1 reach
+// on both sides, and the rounding margins), columns likewise with e_k.
+bool backproject_window_fits(const std::vector<ProjFrame> &frames)
+{
+    for (const ProjFrame &f : frames) {
+        const double sj = 3 * fabs(f.ej[0]) + 7 * fabs(f.ej[1]) + 7 * fabs(f.ej[2]) + 2 * f.lj;
+        const double sk = 3 * fabs(f.ek[0]) + 7 * fabs(f.ek[1]) + 7 * fabs(f.ek[2]) + 2 * f.lk;
+        if (floor(sj) + 3 > kWinMax || floor(sk) + 3 > kWinMax) return false;
+    }
+    return true;
+}
+
 // Pairing pays with four unique segments (C2-like workloads: the adjoint
 // 4.21 -> 3.21 ms at 100^3 / 240 projections).  With eight, its own and
 // mirrored residual loads and accumulators raise the register count from 78
@@ -1332,6 +1598,7 @@ __global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict
 // load latency rather than by VALU issue, measured 10% slower than the
 // unpaired one (5% of it the per-pair barrier), so it is not used there.
 static bool use_inv_pair(const Dims &d) { return d.inv_pair && !d.joseph && d.Up == 4; }
+static bool use_window(const Dims &d) { return d.win_ok && !d.joseph && d.Up == 8; }
 static int backproject_inv_blocks(const Dims &d) { return ((d.nx / 2 + 1) / 2) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
 
 int backproject_blocks(const Dims &d)
@@ -1353,6 +1620,17 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
                                    d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
             else
                 hipLaunchKernelGGL((k_backproject_inv<UP, MT, false>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
+                                   d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (UP == 8) {
+        if (use_window(d)) {
+            if (bf16)
+                hipLaunchKernelGGL((k_backproject_win<UP, MT, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
+                                   d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            else
+                hipLaunchKernelGGL((k_backproject_win<UP, MT, false>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
                                    d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
             return hipGetLastError();
         }

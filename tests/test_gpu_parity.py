@@ -58,6 +58,10 @@ CASES = {
     # outside the volume
     "odd_projection_count": lambda: small(ell_max=4, n_rot=5),
     "paired_l8_ragged": lambda: small(ell_max=8, n=(18, 13, 11), n_rot=3),
+    # eight unique segments: the adjoint stages each brick's residual window in
+    # LDS (detector offsets, a non-unit step, steep tilts)
+    "tiny_offsets_step_seg16": lambda: tiny(offsets=True, step=0.8, n_seg=16),
+    "steep_seg16": lambda: steep(n_seg=16),
 }
 
 
