@@ -289,6 +289,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     // KiB for more (measured best of 32/48/64 KiB on 100^3 x 4 and 256^3 x 8)
     d.march_lds = plan_slabs(c->frames, d.Up, (d.Up == 4 ? 32 : 64) * 1024);
     d.win_ok = backproject_window_fits(c->frames) ? 1 : 0;
+    d.pw_lds = backproject_pw_lds(c->frames, d.Up, d.pw_wr, d.pw_wc);
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

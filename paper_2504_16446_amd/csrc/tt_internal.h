@@ -91,6 +91,8 @@ struct Dims {
                         //    voxel pair (v, -v) once
     int win_ok;         // 1: every projection's residual window of a 4 x 8 x 8 brick fits the
                         //    adjoint's LDS window (trilinear model, eight unique segments)
+    int pw_lds, pw_wr, pw_wc;  // paired + windowed adjoint: dynamic LDS bytes (0: not used) and
+                               // window rows / columns
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
@@ -119,6 +121,7 @@ hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const floa
 int backproject_blocks(const Dims &d);
 int backproject_blocks_max(const Dims &d);
 bool backproject_window_fits(const std::vector<ProjFrame> &frames);
+int backproject_pw_lds(const std::vector<ProjFrame> &frames, int up, int &wr, int &wc);
 
 // Derived per-voxel quantities: out[v][kPropFields] from c[v][C] (tt_props.hip).
 constexpr int kPropFields = 22;

@@ -1578,6 +1578,305 @@ __global__ __launch_bounds__(256) void k_backproject_win(const float *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// backproject, paired by point inversion and with LDS-staged residual windows
+// (trilinear model, centred detector, even nx, eight unique segments).  Block
+// as in k_backproject_inv: waves 0, 1 own two lower-half x-slices, waves 2, 3
+// their inverses; per pair of projections (s0, s0 + 1) the lower group
+// enumerates s0 and the upper group s0 + 1.  Each group stages, for its
+// projection, the residual window of its own 2 x 8 x 8 voxels and the
+// point-reflected window (row nj-1-j, column nk-1-k at the position of
+// (j, k)), so a ray's own and mirrored reads use the same offset in two LDS
+// buffers.  The copies for the next pair are issued before this pair's
+// MFMAs.  Two block barriers per pair: windows staged, Q handed over.
+// ---------------------------------------------------------------------------
+template <int UP, int MT, bool BF16>
+__global__ __launch_bounds__(256) void k_backproject_pw(const float *__restrict__ yf,
+                                                        const ProjFrame *__restrict__ frames,
+                                                        const float *__restrict__ Bu, const s4 *__restrict__ BuT16,
+                                                        int S, int nx, int ny, int nz, int nj, int nk, int C, int Cp,
+                                                        float step, float *__restrict__ g, float beta,
+                                                        const float *__restrict__ c, double *__restrict__ partials,
+                                                        int WR, int WC)
+{
+    constexpr int Q = UP / 4;
+    constexpr int QS = 64 * (UP + 1);
+    extern __shared__ f4 wins[];     // [group][own, reflected][WR][WC][Q]
+    __shared__ float Qs[4][QS];      // each wave's own Q
+    __shared__ float Qx[4][QS];      // Q handed over by the partner wave
+    __shared__ double ws[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool upper = wave >= 2;
+    const int grp = upper ? 1 : 0;
+    const int nxh = nx >> 1;
+    const int nbx = (nxh + 1) / 2, nby = (ny + 7) / 8;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+    const int px = bx * 2 + (wave & 1), py = by * 8 + (lane >> 3), pz = bz * 8 + (lane & 7);
+    const bool valid = px < nxh && py < ny && pz < nz;
+    const int ix = upper ? nx - 1 - px : px, iy = upper ? ny - 1 - py : py, iz = upper ? nz - 1 - pz : pz;
+    const double xv[3] = {ix - 0.5 * (nx - 1), iy - 0.5 * (ny - 1), iz - 0.5 * (nz - 1)};
+    const double inv_step = 1.0 / (double)step;
+    const float stepf = step, inv_stepf = (float)inv_step;
+    const int WROW = WC * Q, WSZ = WR * WROW;
+    f4 *win_own = wins + (2 * grp) * WSZ, *win_ref = wins + (2 * grp + 1) * WSZ;
+
+    // window of this group's voxel box for projection s (its L1 reach lj, lk
+    // around the detector positions, one more on each side for rounding)
+    auto window = [&](int s, int &j0, int &k0, int &nr, int &nc) {
+        const ProjFrame &f = frames[s];
+        const double lo0[3] = {bx * 2 - 0.5 * (nx - 1), by * 8 - 0.5 * (ny - 1), bz * 8 - 0.5 * (nz - 1)};
+        const double hi0[3] = {min(nxh, bx * 2 + 2) - 1 - 0.5 * (nx - 1), min(ny, by * 8 + 8) - 1 - 0.5 * (ny - 1),
+                               min(nz, bz * 8 + 8) - 1 - 0.5 * (nz - 1)};
+        double amin = 0.0, amax = 0.0, bmin = 0.0, bmax = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // the upper group's box is the point inverse of the lower group's
+            const double lo = upper ? -hi0[a] : lo0[a], hi = upper ? -lo0[a] : hi0[a];
+            const double ea = f.ej[a], ka = f.ek[a];
+            amin += (ea >= 0.0 ? lo - f.o[a] : hi - f.o[a]) * ea;
+            amax += (ea >= 0.0 ? hi - f.o[a] : lo - f.o[a]) * ea;
+            bmin += (ka >= 0.0 ? lo - f.o[a] : hi - f.o[a]) * ka;
+            bmax += (ka >= 0.0 ? hi - f.o[a] : lo - f.o[a]) * ka;
+        }
+        const int ja = max(0, (int)ceil(amin - f.lj) - 1), jb = min(nj - 1, (int)floor(amax + f.lj) + 1);
+        const int ka0 = max(0, (int)ceil(bmin - f.lk) - 1), kb = min(nk - 1, (int)floor(bmax + f.lk) + 1);
+        j0 = __builtin_amdgcn_readfirstlane(ja);
+        k0 = __builtin_amdgcn_readfirstlane(ka0);
+        nr = __builtin_amdgcn_readfirstlane(max(0, min(WR, jb - ja + 1)));
+        nc = __builtin_amdgcn_readfirstlane(max(0, min(WC, kb - ka0 + 1)));
+    };
+    // asynchronous copies of the window and of its point reflection (rows spread
+    // over the group's two waves)
+    auto stage = [&](int s, int j0, int k0, int nr, int nc) {
+        const f4 *ys = reinterpret_cast<const f4 *>(yf) + (long long)s * nj * nk * Q;
+        const int rowf4 = nc * Q;
+        for (int r = wave & 1; r < nr; r += 2) {
+            for (int l0 = 0; l0 < rowf4; l0 += 64) {
+                const int l = l0 + lane;
+                if (l < rowf4) {
+                    const int cc = l / Q, q = l - cc * Q;
+                    const f4 *so = ys + ((long long)(j0 + r) * nk + k0) * Q + l;
+                    const f4 *sr = ys + ((long long)(nj - 1 - j0 - r) * nk + (nk - 1 - k0 - cc)) * Q + q;
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)so,
+                                                     (__attribute__((address_space(3))) void *)(win_own + r * WROW + l0),
+                                                     16, 0, 0);
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)sr,
+                                                     (__attribute__((address_space(3))) void *)(win_ref + r * WROW + l0),
+                                                     16, 0, 0);
+                }
+            }
+        }
+    };
+
+    f4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+
+    struct BOps {
+        s4 b16[BF16 ? MT : 1];
+        float f[BF16 ? 1 : UP / 4][MT];
+    };
+    auto load_ops = [&](int s, BOps &o) {
+        if constexpr (BF16) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                o.b16[mt] = BuT16[((long long)s * Cp + mt * 16 + (lane & 15)) * 4 + (lane >> 4)];
+        } else {
+            const float *Bs = Bu + (long long)s * UP * Cp;
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o.f[ks][mt] = Bs[(ks * 4 + (lane >> 4)) * Cp + mt * 16 + (lane & 15)];
+        }
+    };
+    auto contract = [&](const BOps &o, const float *Qt) {
+        if constexpr (BF16) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const float *qv = Qt + (nt * 16 + (lane & 15)) * (UP + 1);
+                const int u0 = 4 * (lane >> 4);
+                s4 bv;
+                bv.x = u0 + 0 < UP ? f2bf(qv[min(u0 + 0, UP - 1)]) : (short)0;
+                bv.y = u0 + 1 < UP ? f2bf(qv[min(u0 + 1, UP - 1)]) : (short)0;
+                bv.z = u0 + 2 < UP ? f2bf(qv[min(u0 + 2, UP - 1)]) : (short)0;
+                bv.w = u0 + 3 < UP ? f2bf(qv[min(u0 + 3, UP - 1)]) : (short)0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x16bf16(o.b16[mt], bv, acc[mt][nt]);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < UP / 4; ++ks) {
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const float bv = qw_at<UP>(Qt, nt, ks, lane);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma16x16x4(o.f[ks][mt], bv, acc[mt][nt]);
+                }
+            }
+        }
+    };
+
+    int wj0 = 0, wk0 = 0, wnr = 0, wnc = 0;  // this group's window of the current pair
+    if (grp < S) {
+        window(grp, wj0, wk0, wnr, wnc);
+        stage(grp, wj0, wk0, wnr, wnc);
+    }
+    for (int s0 = 0; s0 < S; s0 += 2) {
+        const int s_own = s0 + grp, s_oth = s0 + 1 - grp;
+        const bool has_own = s_own < S, has_oth = s_oth < S;
+        BOps ops_own, ops_oth;
+        load_ops(has_own ? s_own : s0, ops_own);
+        load_ops(has_oth ? s_oth : s0, ops_oth);
+        float q[UP], qm[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) q[u] = qm[u] = 0.0f;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // this pair's windows are staged
+        if (has_own && valid) {
+            const ProjFrame &f = frames[s_own];
+            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+            const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
+            const double af = floor(a), bf = floor(bb), tf = floor(ts);
+            const int ai = (int)af, bi = (int)bf;
+            const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
+            const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
+            float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
+            asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
+            float dfv[3] = {f.df[0], f.df[1], f.df[2]};
+            asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
+            const float ljf = (float)f.lj;
+            const int jlo = max(wj0, ai + (int)ceilf(ar - ljf));
+            const int jhi = min(wj0 + wnr - 1, ai + (int)floorf(ar + ljf));
+            const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
+            const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
+            for (int j = jlo; j <= jhi; ++j) {
+                const float dj = (float)(j - ai) - ar;
+                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
+                                         fmaf(f.hull[4], dj, cu[2]));
+                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
+                                         fmaf(f.hull[10], dj, cl[2]));
+                const int klo = max(wk0, bi + (int)ceilf(zmin));
+                const int khi = min(wk0 + wnc - 1, bi + (int)floorf(zmax));
+                const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
+                const int rowoff = (j - wj0) * WROW - wk0 * Q;
+                const f4 *wo = win_own + rowoff, *wr = win_ref + rowoff;
+                float dk = (float)(klo - bi) - br;
+                for (int k = klo; k <= khi; ++k, dk += 1.0f) {
+                    f4 yv[Q], ym[Q];
+#pragma unroll
+                    for (int u4 = 0; u4 < Q; ++u4) {
+                        yv[u4] = wo[k * Q + u4];
+                        ym[u4] = wr[k * Q + u4];
+                    }
+                    const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
+                    float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+#pragma unroll
+                    for (int m = 1; m < 3; ++m) {
+                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
+                        thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                    }
+                    float wsum = 0.0f;
+                    const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
+                    const float tend = (m1 - tr + 0.5f) * stepf;
+                    for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
+                        const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
+                        const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
+                        const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
+                        wsum = fmaf(wx * wy, wz, wsum);
+                    }
+#pragma unroll
+                    for (int u4 = 0; u4 < UP; u4 += 4) {
+                        q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
+                        q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
+                        q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
+                        q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
+                        qm[u4 + 0] = fmaf(wsum, ym[u4 / 4].x, qm[u4 + 0]);
+                        qm[u4 + 1] = fmaf(wsum, ym[u4 / 4].y, qm[u4 + 1]);
+                        qm[u4 + 2] = fmaf(wsum, ym[u4 / 4].z, qm[u4 + 2]);
+                        qm[u4 + 3] = fmaf(wsum, ym[u4 / 4].w, qm[u4 + 3]);
+                    }
+                }
+            }
+        }
+        float *Qown = Qs[wave];
+        float *Qout = Qx[wave ^ 2];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            Qown[lane * (UP + 1) + u] = q[u];
+            Qout[lane * (UP + 1) + u] = qm[u];
+        }
+        __syncthreads();  // the partner's Q is complete; the windows are free
+        // copies for the next pair run during this pair's MFMAs
+        const int s_next = s0 + 2 + grp;
+        if (s_next < S) {
+            window(s_next, wj0, wk0, wnr, wnc);
+            stage(s_next, wj0, wk0, wnr, wnc);
+        }
+        if (has_own) contract(ops_own, Qown);
+        if (has_oth) contract(ops_oth, Qx[wave]);
+    }
+
+    double c2 = 0.0;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int lv = nt * 16 + (lane & 15);
+        const int qy = by * 8 + (lv >> 3), qz = bz * 8 + (lv & 7);
+        if (px < nxh && qy < ny && qz < nz) {
+            const int vx = ix, vy = upper ? ny - 1 - qy : qy, vz = upper ? nz - 1 - qz : qz;
+            const long long base = (((long long)vx * ny + vy) * nz + vz) * C;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mt * 16 + 4 * (lane >> 4) + r;
+                    if (i < C) {
+                        float val = acc[mt][nt][r];
+                        if (c) {
+                            float cv = c[base + i];
+                            val += beta * cv;
+                            c2 += (double)cv * (double)cv;
+                        }
+                        g[base + i] = val;
+                    }
+                }
+            }
+        }
+    }
+    if (partials) {
+        double tot = block_sum(c2, ws);
+        if (tid == 0) partials[bid] = tot;
+    }
+}
+
+// Window extent (rows, columns) of a voxel box with centre spans (sx, sy, sz)
+// over the projections: span . |e| + 2 l + 3 (L1 reach on both sides and the
+// rounding margins); 0 if some projection exceeds lim.
+static void window_extent(const std::vector<ProjFrame> &frames, double sx, double sy, double sz, int &wr, int &wc)
+{
+    wr = wc = 0;
+    for (const ProjFrame &f : frames) {
+        const double sj = sx * fabs(f.ej[0]) + sy * fabs(f.ej[1]) + sz * fabs(f.ej[2]) + 2 * f.lj;
+        const double sk = sx * fabs(f.ek[0]) + sy * fabs(f.ek[1]) + sz * fabs(f.ek[2]) + 2 * f.lk;
+        wr = std::max(wr, (int)floor(sj) + 3);
+        wc = std::max(wc, (int)floor(sk) + 3);
+    }
+}
+
+// Paired + windowed adjoint: four windows of wr x wc rays x 8 floats beside
+// 18 KiB of Q tiles must leave three blocks per CU (<= 52 KiB per block).
+int backproject_pw_lds(const std::vector<ProjFrame> &frames, int up, int &wr, int &wc)
+{
+    window_extent(frames, 1.0, 7.0, 7.0, wr, wc);
+    const int bytes = 4 * wr * wc * up * 4;
+    return bytes + 2 * 4 * 64 * (up + 1) * 4 <= 52 * 1024 ? bytes : 0;
+}
+
 // Largest detector window of a 4 x 8 x 8 brick over the projections: rows
 // <= 3|e_jx| + 7|e_jy| + 7|e_jz| + 2 l_j + 3 (the voxel-centre span, the L1 reach
 // on both sides, and the rounding margins), columns likewise with e_k.
@@ -1599,11 +1898,12 @@ bool backproject_window_fits(const std::vector<ProjFrame> &frames)
 // unpaired one (5% of it the per-pair barrier), so it is not used there.
 static bool use_inv_pair(const Dims &d) { return d.inv_pair && !d.joseph && d.Up == 4; }
 static bool use_window(const Dims &d) { return d.win_ok && !d.joseph && d.Up == 8; }
+static bool use_pw(const Dims &d) { return d.pw_lds > 0 && d.inv_pair && !d.joseph && d.Up == 8; }
 static int backproject_inv_blocks(const Dims &d) { return ((d.nx / 2 + 1) / 2) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
 
 int backproject_blocks(const Dims &d)
 {
-    return use_inv_pair(d) ? backproject_inv_blocks(d) : ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
+    return use_inv_pair(d) || use_pw(d) ? backproject_inv_blocks(d) : ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
 }
 int backproject_blocks_max(const Dims &d) { return ((d.nx + 3) / 4) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
 
@@ -1625,6 +1925,17 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
         }
     }
     if constexpr (UP == 8) {
+        if (use_pw(d)) {
+            if (bf16)
+                hipLaunchKernelGGL((k_backproject_pw<UP, MT, true>), grid, block, d.pw_lds, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, d.pw_wr,
+                                   d.pw_wc);
+            else
+                hipLaunchKernelGGL((k_backproject_pw<UP, MT, false>), grid, block, d.pw_lds, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, d.pw_wr,
+                                   d.pw_wc);
+            return hipGetLastError();
+        }
         if (use_window(d)) {
             if (bf16)
                 hipLaunchKernelGGL((k_backproject_win<UP, MT, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
