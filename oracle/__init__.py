@@ -107,7 +107,7 @@ class Geometry:
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame, n_sub=3, step=1.0,
                  seg_span=2 * np.pi, joff=None, koff=None, model="trilinear", basis="sh", dirs=None,
-                 width=None):
+                 width=None, sparse_k=0):
         self.n = tuple(int(v) for v in n)
         self.ell_max = int(ell_max)
         self.inner = _f64(inner)
@@ -144,6 +144,9 @@ class Geometry:
             getattr(g, field)[:] = self.frame[name]
         self._g = g
         self._B = None
+        if sparse_k < 0:
+            raise ValueError("sparse_k must be >= 0 (0: the exact basis constants)")
+        self.sparse_k = int(sparse_k)
 
     @classmethod
     def from_workload(cls, w, **kw):
@@ -174,8 +177,11 @@ class Geometry:
         return C.byref(self._g)
 
     def B(self):
+        """Basis constants in use: the exact B, or its sparse approximation
+        when ``sparse_k`` > 0 (see ``sparse_basis``)."""
         if self._B is None:
-            self._B = basis_matrix(self)
+            B = basis_matrix(self)
+            self._B = sparse_basis(B, self.sparse_k) if self.sparse_k > 0 else B
         return self._B
 
 
@@ -207,6 +213,38 @@ def basis_matrix(g: Geometry):
     B = np.empty((g.n_proj, g.n_seg, g.n_coeff))
     lib().og_basis_matrix(g.ref(), _p(B))
     return B
+
+
+SPARSE_TIE = 1e-9
+
+
+def sparse_basis(B, k, tie=SPARSE_TIE):
+    """Sparse approximation of the basis constants (the sparse variant of the
+    asynchronous pipelines, sect. "Pipelines": the reciprocal-space map is
+    replaced by a sparse approximation so that it can be applied inside the
+    ray sum).  The paper names the approximation without a rule; the reading
+    used here: in every row (projection s, segment c) of B, keep the k entries
+    of largest magnitude and set the others to zero.  Entries are taken one
+    at a time: the largest remaining magnitude m is found, and among the
+    remaining entries with |B| >= m - tie * max|row| the lowest index is
+    kept (so exact and near ties go to the lower basis index).  k >= the row
+    length keeps the whole row."""
+    B = np.asarray(B, dtype=np.float64)
+    out = np.zeros_like(B)
+    C = B.shape[-1]
+    rows = B.reshape(-1, C)
+    res = out.reshape(-1, C)
+    for r in range(rows.shape[0]):
+        row = rows[r]
+        mag = np.abs(row)
+        scale = mag.max()
+        left = list(range(C))
+        for _ in range(min(int(k), C)):
+            m = max(mag[i] for i in left)
+            pick = min(i for i in left if mag[i] >= m - tie * scale)
+            res[r, pick] = row[pick]
+            left.remove(pick)
+    return out
 
 
 def project(g: Geometry, c, B=None):

@@ -12,7 +12,7 @@ import math
 
 import numpy as np
 
-from . import Geometry, basis_matrix, frame
+from . import Geometry, frame
 
 
 def voxel_centres(g: Geometry):
@@ -39,6 +39,6 @@ def dense_P(g: Geometry, s: int):
 
 
 def dense_A(g: Geometry):
-    B = basis_matrix(g)
+    B = g.B()  # the basis constants in use (exact, or their sparse approximation)
     blocks = [np.kron(dense_P(g, s), B[s]) for s in range(g.n_proj)]
     return np.vstack(blocks)
