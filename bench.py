@@ -343,6 +343,41 @@ def joseph_bench(w, dev, reps=3):
             "algorithmic_GBps": bytes_ / (total * 1e-3) / 1e9}
 
 
+def sparse_bench(w, dev, ks=(2, 0), reps=3):
+    """Sparse fused forward (sect. "Pipelines"): the forward with the k
+    largest basis constants per projection and segment in one fused kernel
+    (no mapped volumes), against the two-pass map + march with the exact
+    constants on the same workload.  k = 0 stands for k = C (the exact map
+    evaluated by the fused kernel)."""
+    import torch
+    from paper_2504_16446_amd.projector import Projector
+
+    out = {"workload": w.name}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(98)
+    c = None
+    for k in ks:
+        kk = k if k > 0 else w.n_coeff
+        P = Projector.from_workload(w, device=dev, sparse_k=kk)
+        if c is None:
+            c = torch.randn(P.vol_shape, device=dev, generator=gen)
+        I = P.forward(c)
+        torch.cuda.synchronize()
+        P.timing(True)
+        for _ in range(reps):
+            P.forward(c, out=I)
+        kt = P.timing_read()
+        P.timing(False)
+        ms = kt["fused"][0] / max(kt["fused"][1], 1)
+        out[f"k{kk}"] = {"ms_forward": ms, "workspace_bytes": P.work_bytes,
+                         "algorithmic_GBps": w.n_proj * algorithmic_bytes(w) / (ms * 1e-3) / 1e9}
+        del P, I
+        torch.cuda.empty_cache()
+    del c
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +425,7 @@ def main():
     P = Projector.from_workload(w, device=dev)
     samples = P.ray_samples()
     forward_batch = P.batch
+    work_bytes = P.work_bytes
     c_true_np = phantom.coefficients(w)
     c_true = torch.from_numpy(c_true_np).to(dev)
     data = P.forward(c_true)
@@ -491,6 +527,11 @@ def main():
     joseph = None if args.no_extras else joseph_bench(w, dev)
     print("[bench] regularisers ...", file=sys.stderr, flush=True)
     regs = None if args.no_extras else regulariser_bench(dev)
+    print("[bench] sparse fused forward ...", file=sys.stderr, flush=True)
+    sparse = None if args.no_extras else sparse_bench(w, dev)
+    if sparse is not None:
+        sparse["two_pass_ms_forward"] = sum(kernels[k]["ms_per_step"] for k in ("map", "march") if k in kernels)
+        sparse["two_pass_workspace_bytes"] = work_bytes
 
     line = {
         "metric": "fwd+adj projector GB/s & % HBM roof; time-to-residual warm-start vs plain",
@@ -512,6 +553,7 @@ def main():
         "tensor_properties": props,
         "joseph": joseph,
         "regularisers": regs,
+        "sparse_fused": sparse,
     }
     print(json.dumps(line), flush=True)
 

@@ -121,6 +121,29 @@ int tt_set_stream(tt_ctx *ctx, void *hip_stream);
 /* Select TT_MAP_FP32 or TT_MAP_BF16 for tt_project / tt_adjoint. */
 int tt_set_map_precision(tt_ctx *ctx, int precision);
 
+/* Sparse fused forward (sect. "Pipelines": the sparse variant of the
+ * asynchronous pipelines applies a sparse approximation of the
+ * reciprocal-space map inside the ray-sum kernel, so the intermediate between
+ * the two mappings is never stored; it saves memory rather than time unless
+ * the map is very sparse).
+ *   k = 0 (default): the exact constants B_{sc,i}; tt_project maps a batch of
+ *     projections into the workspace (M_s = B_s c) and ray-sums it.
+ *   k >= 1: in every row (projection s, segment c) of B only the k entries of
+ *     largest magnitude are kept and the others set to zero (taken one at a
+ *     time: the largest remaining magnitude m, then the lowest remaining basis
+ *     index with |B| >= m - 1e-9 max|row|; k >= C keeps B whole); tt_project
+ *     runs one fused kernel for all projections that forms the unique segment
+ *     values sum_t B_{sc,i_t} c_{v,i_t} of each voxel while staging the
+ *     coefficient volume for the ray sums (no mapped volumes in the
+ *     workspace).  tt_adjoint, tt_loss_grad, the solver, tt_kappa and
+ *     tt_basis_matrix use the same approximated constants, so the pair stays
+ *     exactly adjoint.  The constants are rebuilt on the host and uploaded
+ *     (synchronous; waits for the context's stream).
+ * TT_EINVAL for k < 0; TT_EUNSUPPORTED for k >= 1 with Joseph's method or the
+ * bf16 map tier (and tt_set_projector / tt_set_map_precision return
+ * TT_EUNSUPPORTED for those while a sparse map is set). */
+int tt_set_sparse_map(tt_ctx *ctx, int k);
+
 /* Discretisation of the projection operator P_{sjk,xyz} (Eq. projection_operator):
  *   TT_PROJ_TRILINEAR (default): samples every `step` voxels along the ray,
  *     trilinear (tent) weights, each sample weighted by `step`;
@@ -151,10 +174,15 @@ int tt_sizes(const tt_ctx *ctx, int64_t *out8);
  * ((nx+2)(ny+2)(nz+2) U floats each, zero border).  The forward evaluates
  * Eq. forward_model batch by batch: a larger batch reads c fewer times.
  * tt_workspace_bytes gives the bytes for a batch of forward_batch projections
- * (rounded to what the map kernel accepts; forward_batch <= 1 gives the
- * smallest valid workspace, >= n_proj the whole set in one batch).
+ * (rounded to what the map kernel accepts; forward_batch = 1 gives the
+ * smallest valid workspace, >= n_proj the whole set in one batch;
+ * forward_batch <= 0 gives the workspace without mapped volumes, which serves
+ * only the fused forward of tt_set_sparse_map).
  * tt_set_workspace attaches caller memory (device, 256-byte aligned) and
- * picks the largest batch that fits; TT_EINVAL below the smallest size.  The
+ * picks the largest batch that fits; TT_EINVAL below the smallest size (with
+ * a sparse map set, below the size without mapped volumes; tt_project then
+ * returns TT_EINVAL if the sparse map is switched off again while the
+ * attached workspace holds no mapped volume).  The
  * memory must stay allocated and untouched by the caller while attached; the
  * zero border is written once, on the context's stream.  Calls that compute
  * (tt_project, tt_adjoint, tt_loss_grad, the solver, tt_kappa,
@@ -441,7 +469,8 @@ enum {
     TT_K_RESIDUAL = 4,    /* residual, loss partials and fold */
     TT_K_VECTOR = 5,      /* L-BFGS streaming vector passes and reductions */
     TT_K_PLAN = 6,        /* L-BFGS float64 planner kernels */
-    TT_K_COUNT = 7
+    TT_K_FUSED = 7,       /* fused sparse map + ray march, forward (tt_set_sparse_map) */
+    TT_K_COUNT = 8
 };
 int tt_timing_enable(tt_ctx *ctx, int on);
 /* Synchronise, then ms_total[k] = summed duration and launches[k] = number of

@@ -17,7 +17,7 @@ TT_MAP_FP32, TT_MAP_BF16 = 0, 1
 TT_PROJ_TRILINEAR, TT_PROJ_JOSEPH = 0, 1
 TT_BASIS_SH, TT_BASIS_GK, TT_BASIS_NN = 0, 1, 2
 REDUCE_WORK = 4096  # TT_REDUCE_WORK: float64 partials of a value reduction
-KERNEL_CLASSES = ["map", "march", "fold", "backproject", "residual", "vector", "plan"]
+KERNEL_CLASSES = ["map", "march", "fold", "backproject", "residual", "vector", "plan", "fused"]
 _ERRORS = {-1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EUNSUPPORTED"}
 
 
@@ -55,6 +55,7 @@ _SIGS = [
     ("tt_set_stream", C.c_int, [_vp, _vp]),
     ("tt_set_map_precision", C.c_int, [_vp, C.c_int]),
     ("tt_set_projector", C.c_int, [_vp, C.c_int]),
+    ("tt_set_sparse_map", C.c_int, [_vp, C.c_int]),
     ("tt_num_coeffs", C.c_int, [C.c_int]),
     ("tt_sizes", C.c_int, [_vp, C.POINTER(C.c_int64)]),
     ("tt_basis_matrix", C.c_int, [_vp, C.POINTER(C.c_double)]),

@@ -39,8 +39,10 @@ struct tt_ctx {
     hipStream_t stream = nullptr;
     int precision = TT_MAP_FP32;
     std::vector<ProjFrame> frames;
-    std::vector<double> B;  // [S][nseg][C] float64
+    std::vector<double> B;  // [S][nseg][C] float64, the constants in use
+    std::vector<double> B_exact;  // the exact constants (B differs under a sparse map)
     ProjFrame *d_frames = nullptr;
+    int2 *d_sp = nullptr;       // [S][Up][sparse_k] sparse map (basis index, constant bits)
     float *d_Bu = nullptr;      // [bu_rows][Cp]: row s*Up + u, zero padded
     float *d_Bsw = nullptr;     // Bu in MFMA lane order (16-row tiles), for the forward map
     uint16_t *d_Bsw16 = nullptr; // bf16 Bu in MFMA lane order (16-row tiles, k blocks of 16), forward
@@ -113,6 +115,67 @@ static uint16_t to_bf16(float x)
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
     u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
     return (uint16_t)(u >> 16);
+}
+
+// Basis tables in the layouts the kernels read, built from the constants in use (c->B).
+struct Tables {
+    std::vector<float> bu;         // [bu_rows][Cp]: row s*Up + u, zero padded
+    std::vector<float> bsw;        // bu in MFMA lane order: tile rt, k-step ks, lane l
+    std::vector<uint16_t> bsw16;   // bf16 bu in MFMA lane order (16-row tiles, k blocks of 16)
+    std::vector<uint16_t> but16;   // bf16 [S][Cp][16]: B^T with u padded to 16
+};
+static void build_tables(const tt_ctx *c, Tables &t)
+{
+    const Dims &d = c->d;
+    const int S = d.S;
+    const int bu_rows = round_up(S * d.Up, 256) + 256;
+    t.bu.assign((size_t)bu_rows * d.Cp, 0.0f);
+    for (int s = 0; s < S; ++s)
+        for (int u = 0; u < d.U; ++u)
+            for (int i = 0; i < d.C; ++i)
+                t.bu[((size_t)s * d.Up + u) * d.Cp + i] = (float)c->B[((size_t)s * d.nseg + u) * d.C + i];
+    const int KB = d.Cp / 16;
+    t.bsw16.assign(t.bu.size(), 0);
+    t.but16.assign((size_t)S * d.Cp * 16, 0);
+    for (int rt = 0; rt < bu_rows / 16; ++rt)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int l = 0; l < 64; ++l)
+                for (int q = 0; q < 4; ++q)
+                    t.bsw16[(((size_t)rt * KB + kb) * 64 + l) * 4 + q] =
+                        to_bf16(t.bu[((size_t)rt * 16 + l % 16) * d.Cp + 16 * kb + 4 * (l / 16) + q]);
+    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < d.Cp; ++i)
+            for (int u = 0; u < d.Up; ++u)
+                t.but16[((size_t)s * d.Cp + i) * 16 + u] = to_bf16(t.bu[((size_t)s * d.Up + u) * d.Cp + i]);
+    // MFMA-ordered copy of bu: tile rt, k-step ks, lane l -> bu[16 rt + l % 16][4 ks + l / 16]
+    t.bsw.assign(t.bu.size(), 0.0f);
+    const int KS = d.Cp / 4;
+    for (int rt = 0; rt < bu_rows / 16; ++rt)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int l = 0; l < 64; ++l)
+                t.bsw[((size_t)rt * KS + ks) * 64 + l] = t.bu[((size_t)rt * 16 + l % 16) * d.Cp + 4 * ks + l / 16];
+}
+
+// Kept entries of one row of basis constants under the sparse map: taken one
+// at a time, the largest remaining magnitude m first, and among the remaining
+// entries with |B| >= m - 1e-9 max|row| the lowest index.
+static void sparse_select(const double *row, int C, int k, std::vector<int> &keep)
+{
+    double scale = 0.0;
+    for (int i = 0; i < C; ++i) scale = std::max(scale, std::fabs(row[i]));
+    std::vector<char> used(C, 0);
+    keep.clear();
+    for (int n = 0; n < std::min(k, C); ++n) {
+        double m = -1.0;
+        for (int i = 0; i < C; ++i)
+            if (!used[i]) m = std::max(m, std::fabs(row[i]));
+        for (int i = 0; i < C; ++i)
+            if (!used[i] && std::fabs(row[i]) >= m - 1e-9 * scale) {
+                used[i] = 1;
+                keep.push_back(i);
+                break;
+            }
+    }
 }
 
 static long long n_coef(const tt_ctx *c) { return (long long)c->d.nx * c->d.ny * c->d.nz * c->d.C; }
@@ -302,33 +365,15 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         return fail(TT_EHIP, std::string("static scratch lookup: ") + hipGetErrorString(e));
     }
     const int S = d.S;
-    const int bu_rows = round_up(S * d.Up, 256) + 256;
-    std::vector<float> bu((size_t)bu_rows * d.Cp, 0.0f);
-    for (int s = 0; s < S; ++s)
-        for (int u = 0; u < d.U; ++u)
-            for (int i = 0; i < d.C; ++i) bu[((size_t)s * d.Up + u) * d.Cp + i] = (float)c->B[((size_t)s * d.nseg + u) * d.C + i];
-    // bf16 tables: forward operands in MFMA lane order, adjoint B^T with u padded to 16
-    const int KB = d.Cp / 16;
-    std::vector<uint16_t> bsw16(bu.size(), 0), but16((size_t)S * d.Cp * 16, 0);
-    for (int rt = 0; rt < bu_rows / 16; ++rt)
-        for (int kb = 0; kb < KB; ++kb)
-            for (int l = 0; l < 64; ++l)
-                for (int q = 0; q < 4; ++q)
-                    bsw16[(((size_t)rt * KB + kb) * 64 + l) * 4 + q] =
-                        to_bf16(bu[((size_t)rt * 16 + l % 16) * d.Cp + 16 * kb + 4 * (l / 16) + q]);
-    for (int s = 0; s < S; ++s)
-        for (int i = 0; i < d.Cp; ++i)
-            for (int u = 0; u < d.Up; ++u) but16[((size_t)s * d.Cp + i) * 16 + u] = to_bf16(bu[((size_t)s * d.Up + u) * d.Cp + i]);
+    c->B_exact = c->B;
+    Tables t;
+    build_tables(c, t);
     c->vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     c->per_proj = (size_t)c->vol_pad * d.Up * sizeof(float);
-    // MFMA-ordered copy of Bu: tile rt, k-step ks, lane l -> Bu[16 rt + l % 16][4 ks + l / 16]
-    std::vector<float> bsw(bu.size(), 0.0f);
-    const int KS = d.Cp / 4;
-    for (int rt = 0; rt < bu_rows / 16; ++rt)
-        for (int ks = 0; ks < KS; ++ks)
-            for (int l = 0; l < 64; ++l)
-                bsw[((size_t)rt * KS + ks) * 64 + l] = bu[((size_t)rt * 16 + l % 16) * d.Cp + 4 * ks + l / 16];
     c->n_part = 1024 + std::max(4096, backproject_blocks_max(d));
+    const std::vector<float> &bu = t.bu, &bsw = t.bsw;
+    const std::vector<uint16_t> &bsw16 = t.bsw16, &but16 = t.but16;
+    const size_t sp_len = (size_t)S * d.Up * d.C;
 
     auto cleanup = [&](int code, const std::string &msg) {
         tt_destroy(c);
@@ -338,9 +383,10 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         hipMalloc(&c->d_Bu, bu.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bsw, bsw.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bsw16, bsw16.size() * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&c->d_BuT16, but16.size() * sizeof(uint16_t)) != hipSuccess)
+        hipMalloc(&c->d_BuT16, but16.size() * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&c->d_sp, sp_len * sizeof(int2)) != hipSuccess)
         return cleanup(TT_ENOMEM, "device allocation failed");
-    c->table_bytes = sizeof(ProjFrame) * S + bu.size() * 10 + but16.size() * 2;
+    c->table_bytes = sizeof(ProjFrame) * S + bu.size() * 10 + but16.size() * 2 + sp_len * sizeof(int2);
     if (hipMemcpy(c->d_frames, c->frames.data(), sizeof(ProjFrame) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bu, bu.data(), bu.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bsw, bsw.data(), bsw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
@@ -362,6 +408,7 @@ void tt_destroy(tt_ctx *c)
     hipFree(c->d_Bsw);
     hipFree(c->d_Bsw16);
     hipFree(c->d_BuT16);
+    hipFree(c->d_sp);
     delete c;
 }
 
@@ -377,6 +424,8 @@ int tt_set_projector(tt_ctx *c, int model)
     if (!c) return fail(TT_EINVAL, "null context");
     if (model != TT_PROJ_TRILINEAR && model != TT_PROJ_JOSEPH)
         return fail(TT_EINVAL, "model must be TT_PROJ_TRILINEAR or TT_PROJ_JOSEPH");
+    if (model == TT_PROJ_JOSEPH && c->d.sparse_k > 0)
+        return fail(TT_EUNSUPPORTED, "the sparse fused map supports the trilinear projector only");
     c->d.joseph = model == TT_PROJ_JOSEPH;
     // Joseph's cuts carry their own 1/|d_A| weight: no sample-spacing factor
     c->d.step = c->d.joseph ? 1.0f : (float)c->g.step;
@@ -387,7 +436,52 @@ int tt_set_map_precision(tt_ctx *c, int precision)
 {
     if (!c) return fail(TT_EINVAL, "ctx is null");
     if (precision != TT_MAP_FP32 && precision != TT_MAP_BF16) return fail(TT_EINVAL, "bad precision");
+    if (precision == TT_MAP_BF16 && c->d.sparse_k > 0)
+        return fail(TT_EUNSUPPORTED, "the sparse fused map runs in float32 only");
     c->precision = precision;
+    return TT_OK;
+}
+
+int tt_set_sparse_map(tt_ctx *c, int k)
+{
+    if (!c) return fail(TT_EINVAL, "ctx is null");
+    if (k < 0) return fail(TT_EINVAL, "k must be >= 0");
+    const Dims &d = c->d;
+    if (k > 0 && d.joseph) return fail(TT_EUNSUPPORTED, "the sparse fused map supports the trilinear projector only");
+    if (k > 0 && c->precision == TT_MAP_BF16) return fail(TT_EUNSUPPORTED, "the sparse fused map runs in float32 only");
+    const int kk = std::min(k, d.C);
+    std::vector<int2> sp;
+    if (k == 0) {
+        c->B = c->B_exact;
+    } else {
+        // rows u < U; with an antipodal fold the rows c = u + U (same constants) copy row u
+        sp.assign((size_t)d.S * d.Up * kk, int2{0, 0});
+        std::vector<int> keep;
+        for (int s = 0; s < d.S; ++s)
+            for (int u = 0; u < d.U; ++u) {
+                const double *row = &c->B_exact[((size_t)s * d.nseg + u) * d.C];
+                sparse_select(row, d.C, kk, keep);
+                std::vector<double> sparse(d.C, 0.0);
+                for (size_t t = 0; t < keep.size(); ++t) {
+                    sparse[keep[t]] = row[keep[t]];
+                    const float w = (float)row[keep[t]];
+                    int wb;
+                    std::memcpy(&wb, &w, 4);
+                    sp[((size_t)s * d.Up + u) * kk + t] = int2{keep[t], wb};
+                }
+                for (int cs = u; cs < d.nseg; cs += d.U)
+                    std::memcpy(&c->B[((size_t)s * d.nseg + cs) * d.C], sparse.data(), sizeof(double) * d.C);
+            }
+    }
+    Tables t;
+    build_tables(c, t);
+    TT_HIP(hipStreamSynchronize(c->stream));  // queued kernels may still read the tables
+    TT_HIP(hipMemcpy(c->d_Bu, t.bu.data(), t.bu.size() * sizeof(float), hipMemcpyHostToDevice));
+    TT_HIP(hipMemcpy(c->d_Bsw, t.bsw.data(), t.bsw.size() * sizeof(float), hipMemcpyHostToDevice));
+    TT_HIP(hipMemcpy(c->d_Bsw16, t.bsw16.data(), t.bsw16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    TT_HIP(hipMemcpy(c->d_BuT16, t.but16.data(), t.but16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    if (!sp.empty()) TT_HIP(hipMemcpy(c->d_sp, sp.data(), sp.size() * sizeof(int2), hipMemcpyHostToDevice));
+    c->d.sparse_k = k == 0 ? 0 : kk;
     return TT_OK;
 }
 
@@ -489,6 +583,7 @@ static Scratch attached(const tt_ctx *c) { return {c->d_part, c->d_yf, c->d_resi
 int64_t tt_workspace_bytes(const tt_ctx *c, int forward_batch)
 {
     if (!c) return fail(TT_EINVAL, "ctx is null");
+    if (forward_batch <= 0) return (int64_t)ws_layout(c, 0).total;  // no mapped volumes (fused forward only)
     int pb = batch_round_down(c, std::min(forward_batch, c->d.S));
     pb = std::max(pb, batch_min(c));
     return (int64_t)ws_layout(c, pb).total;
@@ -501,10 +596,13 @@ int tt_set_workspace(tt_ctx *c, void *work, size_t bytes)
     if (reinterpret_cast<uintptr_t>(work) % 256) return fail(TT_EINVAL, "workspace must be 256-byte aligned");
     const size_t base = ws_layout(c, 0).total;
     const long long fit = bytes > base ? (long long)((bytes - base) / c->per_proj) : 0;
-    const int pb = batch_round_down(c, fit);
-    if (pb < batch_min(c))
-        return fail(TT_EINVAL, "workspace of " + std::to_string(bytes) + " bytes is below the minimum of " +
-                                   std::to_string(tt_workspace_bytes(c, 1)));
+    int pb = batch_round_down(c, fit);
+    if (pb < batch_min(c)) {
+        if (c->d.sparse_k == 0 || bytes < base)
+            return fail(TT_EINVAL, "workspace of " + std::to_string(bytes) + " bytes is below the minimum of " +
+                                       std::to_string(c->d.sparse_k ? base : (size_t)tt_workspace_bytes(c, 1)));
+        pb = 0;  // the fused forward needs no mapped volumes
+    }
     const WsLayout L = ws_layout(c, pb);
     c->ws = static_cast<char *>(work);
     c->ws_bytes = bytes;
@@ -514,7 +612,7 @@ int tt_set_workspace(tt_ctx *c, void *work, size_t bytes)
     c->d_resid = reinterpret_cast<float *>(c->ws + L.resid);
     c->d_M = reinterpret_cast<float *>(c->ws + L.M);
     // the map writes only interior voxels: the border of every mapped volume stays zero
-    TT_HIP(hipMemsetAsync(c->d_M, 0, c->per_proj * (size_t)pb, c->stream));
+    if (pb > 0) TT_HIP(hipMemsetAsync(c->d_M, 0, c->per_proj * (size_t)pb, c->stream));
     return TT_OK;
 }
 
@@ -580,6 +678,18 @@ int tt_basis_matrix(const tt_ctx *c, double *B_host)
 
 static int project_sc(tt_ctx *c, const Scratch &sc, const float *cin, float *I)
 {
+    if (c->d.sparse_k > 0) {
+        hipError_t e;
+        {
+            KTimer t(c, TT_K_FUSED, sc.timed);
+            e = launch_march_fused(c->d, c->d_frames, cin, c->d_sp, I, c->stream);
+        }
+        if (e != hipSuccess) return fail(TT_EHIP, std::string("fused march: ") + hipGetErrorString(e));
+        return TT_OK;
+    }
+    if (sc.pb < 1)
+        return fail(TT_EINVAL, "the attached workspace holds no mapped volumes; attach one sized by "
+                               "tt_workspace_bytes with a forward batch >= 1");
     for (int s0 = 0; s0 < c->d.S; s0 += sc.pb) {
         const int np = std::min(sc.pb, c->d.S - s0);
         hipError_t e;
@@ -686,9 +796,11 @@ int tt_loss_grad_noalloc(tt_ctx *c, const float *cin, const float *data, const f
     }
     const size_t cap = kStaticScratchBytes;
     const long long fit = cap > L.total ? (long long)((cap - L.total) / c->per_proj) : 0;
-    const int pb = batch_round_down(c, fit);
-    if (pb < batch_min(c))
-        return fail(TT_ENOMEM, "problem needs " + std::to_string(L.total + c->per_proj * (size_t)batch_min(c)) +
+    const bool fused = c->d.sparse_k > 0;  // the fused forward maps nothing
+    const int pb = fused ? 0 : batch_round_down(c, fit);
+    if (fused ? L.total > cap : pb < batch_min(c))
+        return fail(TT_ENOMEM, "problem needs " +
+                                   std::to_string(L.total + (fused ? 0 : c->per_proj * (size_t)batch_min(c))) +
                                    " bytes of scratch, above the static limit of " + std::to_string(cap) +
                                    " bytes; use tt_loss_grad with a workspace");
     Scratch sc;
@@ -700,7 +812,7 @@ int tt_loss_grad_noalloc(tt_ctx *c, const float *cin, const float *data, const f
     sc.timed = false;
     // the map writes interior voxels only; the array holds whatever the last
     // call on this device left there, so the zero border is restored each time
-    TT_HIP(launch_zero(sc.M, c->per_proj * (size_t)pb, c->stream));
+    if (pb > 0) TT_HIP(launch_zero(sc.M, c->per_proj * (size_t)pb, c->stream));
     return loss_grad_sc(c, sc, cin, data, w, mu, loss, grad, resid);
 }
 

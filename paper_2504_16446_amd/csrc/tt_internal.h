@@ -93,6 +93,8 @@ struct Dims {
                         //    adjoint's LDS window (trilinear model, eight unique segments)
     int pw_lds, pw_wr, pw_wc;  // paired + windowed adjoint: dynamic LDS bytes (0: not used) and
                                // window rows / columns
+    int sparse_k = 0;   // 0: exact basis constants, map + march; >= 1: kept basis functions per
+                        //    (projection, segment) of the sparse map, fused forward
 };
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
@@ -103,6 +105,11 @@ hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bsw16,
 // I[s0+p][j][k][c] = step * ray sums of M[p] along the rays of projection s0+p.
 hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np,
                         float *I, hipStream_t st);
+// Fused sparse forward: I[s][j][k][c] = step * ray sums over projection s of
+// m_u(v) = sum_t w_t c[v][i_t] with (i_t, w_t) = sp[s][u][t] (int2: basis index,
+// float bits), t < d.sparse_k, u = c mod U; all projections in one launch.
+hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp, float *I,
+                              hipStream_t st);
 // yf[s][j][k][u] = scale * sum_{c: c mod U = u} y[s][j][k][c] (optionally
 // y = 2 w (Ip - data) with the loss partials, see launch_residual_fold).
 hipError_t launch_fold(const Dims &d, const float *y, float scale, float *yf, hipStream_t st);

@@ -443,18 +443,67 @@ __device__ __forceinline__ void march_global(const float *__restrict__ Mp, const
     }
 }
 
+// Global-memory march of the fused sparse forward: at every sample the 8
+// corner voxels' coefficients are mapped to the unique segments with the
+// projection's sparse map (tab[u * kk + t] = (basis index, constant)).
+template <int UP>
+__device__ __forceinline__ void march_global_fused(const float *__restrict__ cv, const int2 *tab, int kk, int C,
+                                                   const double b[3], const double ds[3], int n0, int n1, int nx,
+                                                   int ny, int nz, int U, float acc[UP])
+{
+    for (int n = n0; n <= n1; ++n) {
+        const double px = fma((double)n, ds[0], b[0]);
+        const double py = fma((double)n, ds[1], b[1]);
+        const double pz = fma((double)n, ds[2], b[2]);
+        // padded cell [i, i + 1] holds voxels i - 1 and i along each axis
+        const int ix = min(max((int)floor(px), 0), nx);
+        const int iy = min(max((int)floor(py), 0), ny);
+        const int iz = min(max((int)floor(pz), 0), nz);
+        const float fx = (float)(px - ix), fy = (float)(py - iy), fz = (float)(pz - iz);
+        const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+        for (int cc = 0; cc < 8; ++cc) {
+            const int x = ix - 1 + (cc >> 2), y = iy - 1 + ((cc >> 1) & 1), z = iz - 1 + (cc & 1);
+            if ((unsigned)x >= (unsigned)nx || (unsigned)y >= (unsigned)ny || (unsigned)z >= (unsigned)nz) continue;
+            const float wc = ((cc & 4) ? fx : gx) * ((cc & 2) ? fy : gy) * ((cc & 1) ? fz : gz);
+            const float *src = cv + ((long long)(x * ny + y) * nz + z) * C;
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                if (u < U) {
+                    float v = 0.0f;
+                    for (int t = 0; t < kk; ++t) {
+                        const int2 e = tab[u * kk + t];
+                        v = fmaf(__int_as_float(e.y), src[e.x], v);
+                    }
+                    acc[u] = fmaf(wc, v, acc[u]);
+                }
+            }
+        }
+    }
+}
+
 // With 4 unique segments (32 KiB boxes) five blocks fit a CU's LDS; asking
 // for five waves per SIMD (a small spill of setup values) measured 4% faster
 // than the four that 116 VGPRs allow.  Larger UP keep their registers: their
 // spills were much larger and slower.
-template <int UP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UP == 4 ? 5 : 1))) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
+//
+// FUSED: the sparse variant of the forward (sect. "Pipelines": the
+// reciprocal-space map applied inside the ray-sum kernel, so no mapped volume
+// is stored).  M is then the coefficient volume c[nx][ny][nz][C] itself, the
+// grid covers all projections (s0 = 0), and each staged box voxel's unique
+// segment values are formed while staging, m_u = sum_t tab[u][t].w *
+// c[v][tab[u][t].i] over the kk kept basis functions of (s, u); one thread
+// stages one (voxel, segment) pair.  The gather from the box is the same.
+template <int UP, bool FUSED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 && !FUSED) ? 5 : 1))) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
                                                int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
-                                               float step, long long vol_pad, float *__restrict__ I)
+                                               float step, long long vol_pad, float *__restrict__ I,
+                                               const int2 *__restrict__ sp, int kk, int C)
 {
     constexpr int Q = UP / 4;      // float4 per staged voxel
-    extern __shared__ f4 box[];    // [Q][W + 1][eb][ez]
+    extern __shared__ f4 lds[];    // FUSED: the map table int2[UP][kk], then the box
     __shared__ int arange[2];
+    const int tab_f4 = FUSED ? (UP * kk * 8 + 15) / 16 : 0;
+    f4 *box = lds + tab_f4;        // [Q][W + 1][eb][ez]
     const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
     const int lb = blockIdx.x;
     const int p = lb / (ntj * ntk), s = s0 + p;
@@ -463,7 +512,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UP == 4 ? 5
     const int k = tk * kMarchTile + (threadIdx.x / kMarchTile);
     const bool live = j < nj && k < nk;
     const ProjFrame &f = frames[s];
-    const float *Mp = M + (long long)p * vol_pad * UP;
+    const float *Mp = FUSED ? M : M + (long long)p * vol_pad * UP;
+    int2 *tab = reinterpret_cast<int2 *>(lds);
+    if constexpr (FUSED) {
+        const int2 *src = sp + (long long)s * UP * kk;
+        for (int i = threadIdx.x; i < UP * kk; i += 256) tab[i] = src[i];
+        __syncthreads();
+    }
     double b[3], ds[3];
     int n0 = 0, n1 = -1;
     if (live) ray_setup(f, j, k, nx, ny, nz, step, b, ds, n0, n1);
@@ -473,7 +528,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UP == 4 ? 5
 
     const int W = f.slab_w;
     if (W == 0) {
-        if (n0 <= n1) march_global<UP>(Mp, b, ds, n0, n1, nx, ny, nz, acc);
+        if (n0 <= n1) {
+            if constexpr (FUSED)
+                march_global_fused<UP>(M, tab, kk, C, b, ds, n0, n1, nx, ny, nz, U, acc);
+            else
+                march_global<UP>(Mp, b, ds, n0, n1, nx, ny, nz, acc);
+        }
     } else {
         const int A = f.slab_a, B = 1 - A, EB = f.slab_eb, EZ = f.slab_ez;
         // samples are visited in increasing index coordinate along A
@@ -541,21 +601,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UP == 4 ? 5
         int m = 0;
         for (int A0 = amin; A0 <= amax; A0 += W) {
             const int B0 = (int)floor(fma((double)A0, rB, kb)) - 1, Z0 = (int)floor(fma((double)A0, rZ, kz)) - 1;
-            const f4 *src0 = reinterpret_cast<const f4 *>(Mp) + ((long long)A0 * sA + (long long)B0 * sB + Z0) * Q;
             __syncthreads();  // the previous slab's gathers are done
+            if constexpr (FUSED) {
+                // work item (box voxel e, segment u = thread mod UP), VS voxels per pass
+                constexpr int VS = 256 / UP;
+                const int u = threadIdx.x & (UP - 1);
+                float *boxf = reinterpret_cast<float *>(box) + (long long)(u >> 2) * nbox * 4 + (u & 3);
+                const int2 *tu = tab + u * kk;
+                const int v0 = threadIdx.x / UP;
+                int pl = v0 / plane, ib = (v0 - pl * plane) / EZ, iz = v0 - pl * plane - ib * EZ;
+                const int t_pl = VS / plane, t_r = VS - t_pl * plane, t_ib = t_r / EZ, t_iz = t_r - t_ib * EZ;
+                const int nA = A == 0 ? nx : ny, nB = A == 0 ? ny : nx;
+                for (int e = v0; e < nbox; e += VS) {
+                    const int a = A0 + pl - 1, bq = B0 + ib - 1, z = Z0 + iz - 1;
+                    float v = 0.0f;
+                    if (u < U && (unsigned)a < (unsigned)nA && (unsigned)bq < (unsigned)nB && (unsigned)z < (unsigned)nz) {
+                        const int x = A == 0 ? a : bq, y = A == 0 ? bq : a;
+                        const float *src = M + ((long long)(x * ny + y) * nz + z) * C;
+#pragma unroll 4
+                        for (int t = 0; t < kk; ++t) {
+                            const int2 te = tu[t];
+                            v = fmaf(__int_as_float(te.y), src[te.x], v);
+                        }
+                    }
+                    boxf[e * 4] = v;
+                    pl += t_pl;
+                    ib += t_ib;
+                    iz += t_iz;
+                    if (iz >= EZ) {
+                        iz -= EZ;
+                        ++ib;
+                    }
+                    if (ib >= EB) {
+                        ib -= EB;
+                        ++pl;
+                    }
+                }
+            } else {
+            const f4 *src0 = reinterpret_cast<const f4 *>(Mp) + ((long long)A0 * sA + (long long)B0 * sB + Z0) * Q;
             constexpr int KB = 4;  // staged voxels per thread in flight
             int pl = e_pl, ib = e_ib, iz = e_iz, off = e_pl * sA + e_ib * sB + e_iz;
             for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * KB) {
                 f4 v[KB][Q];
 #pragma unroll
-                for (int kk = 0; kk < KB; ++kk) {
-                    const int e = e0 + 256 * kk;
+                for (int kb = 0; kb < KB; ++kb) {
+                    const int e = e0 + 256 * kb;
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) v[kk][q] = f4{0.f, 0.f, 0.f, 0.f};
+                    for (int q = 0; q < Q; ++q) v[kb][q] = f4{0.f, 0.f, 0.f, 0.f};
                     if (e < nbox && (unsigned)(A0 + pl) <= nAp && (unsigned)(B0 + ib) <= nBp &&
                         (unsigned)(Z0 + iz) <= nZp) {
 #pragma unroll
-                        for (int q = 0; q < Q; ++q) v[kk][q] = src0[off * Q + q];
+                        for (int q = 0; q < Q; ++q) v[kb][q] = src0[off * Q + q];
                     }
                     // advance by 256 elements
                     pl += s_pl;
@@ -574,13 +670,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UP == 4 ? 5
                     }
                 }
 #pragma unroll
-                for (int kk = 0; kk < KB; ++kk) {
-                    const int e = e0 + 256 * kk;
+                for (int kb = 0; kb < KB; ++kb) {
+                    const int e = e0 + 256 * kb;
                     if (e < nbox) {
 #pragma unroll
-                        for (int q = 0; q < Q; ++q) box[q * nbox + e] = v[kk][q];
+                        for (int q = 0; q < Q; ++q) box[q * nbox + e] = v[kb][q];
                     }
                 }
+            }
             }
             __syncthreads();
             // samples of this slab: index position along A below A0 + W
@@ -718,9 +815,32 @@ static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M
                            d.nz, d.nj, d.nk, d.nseg, d.U, vol_pad, I);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_march<UP>, grid, dim3(kMarchTile * kMarchTile), d.march_lds, st, M, frames, s0, d.nx, d.ny,
-                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I);
+    hipLaunchKernelGGL((k_march<UP, false>), grid, dim3(kMarchTile * kMarchTile), d.march_lds, st, M, frames, s0,
+                       d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I, nullptr, 0, 0);
     return hipGetLastError();
+}
+
+template <int UP>
+static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp, float *I,
+                                hipStream_t st)
+{
+    dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * d.S);
+    const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + d.march_lds;
+    hipLaunchKernelGGL((k_march<UP, true>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx, d.ny,
+                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C);
+    return hipGetLastError();
+}
+
+hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp, float *I,
+                              hipStream_t st)
+{
+    if (d.sparse_k < 1 || d.joseph) return hipErrorInvalidValue;
+    switch (d.Up) {
+    case 4: return march_fused_t<4>(d, frames, c, sp, I, st);
+    case 8: return march_fused_t<8>(d, frames, c, sp, I, st);
+    case 16: return march_fused_t<16>(d, frames, c, sp, I, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, int s0, int np, float *I,

@@ -53,12 +53,15 @@ class Projector:
     """Forward model I = A c, adjoint and loss gradient for one geometry.
 
     Shapes: coefficients ``(nx, ny, nz, C)``, data ``(n_proj, nj, nk, n_seg)``.
+    ``sparse_k`` >= 1 selects the sparse fused forward (``tt_set_sparse_map``):
+    the k largest-magnitude basis constants of every projection and segment are
+    kept, and the forward needs no mapped-volume workspace.
     """
 
     def __init__(self, n, ell_max, inner, outer, nj, nk, n_seg, frame=None, n_sub=3, step=1.0,
                  seg_span=2 * math.pi, joff=None, koff=None, map_precision="fp32", device=None,
                  model="trilinear", basis="sh", dirs=None, width=None, forward_batch=None,
-                 workspace_budget=None):
+                 workspace_budget=None, sparse_k=0):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("Projector runs on a HIP device only")
@@ -100,13 +103,18 @@ class Projector:
         call("tt_set_projector", self._h,
              _lib.TT_PROJ_JOSEPH if model == "joseph" else _lib.TT_PROJ_TRILINEAR)
         self.model = model
+        # sparse_k >= 1: the sparse fused forward (no mapped volumes in the workspace)
+        self.sparse_k = int(sparse_k)
+        call("tt_set_sparse_map", self._h, self.sparse_k)
         # Workspace (device memory owned here, handed to the library): the
         # forward maps `forward_batch` projections per pass; by default as many
         # as fit a budget of 1/8 of the free device memory, clamped to [1, 24] GiB.
         sizes = (C.c_int64 * 8)()
         call("tt_sizes", self._h, sizes)
         per_proj = int(sizes[7])
-        if forward_batch is None:
+        if self.sparse_k > 0:
+            forward_batch = 0
+        elif forward_batch is None:
             if workspace_budget is None:
                 free, _ = torch.cuda.mem_get_info(self.device)
                 workspace_budget = min(24 << 30, max(1 << 30, free // 8))

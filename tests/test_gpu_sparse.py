@@ -1,0 +1,209 @@
+"""GPU parity of the sparse fused forward (sect. "Pipelines", the sparse
+variant of the asynchronous pipelines) against the FP64 oracle evaluated with
+the same sparse approximation of the basis constants.
+
+The fused kernel forms each staged voxel's unique segment values from the k
+kept basis functions while staging the coefficient volume for the ray sums;
+the adjoint is the ordinary backprojection with the approximated constants.
+Tolerance as for the dense path: relative L2 <= 1e-5 per output tensor and
+largest element error <= 1e-4 of the largest element (float32 vs float64).
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from geoms import degenerate, small, steep, tiny, workload
+from helpers import gpu_projector, rel_l2, rel_max
+import tt_inputs as synth
+from paper_2504_16446_amd._lib import TTError, call
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = 1e-5
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32), device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _inputs(og, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(og.vol_shape).astype(np.float32).astype(np.float64)
+    y = rng.standard_normal(og.data_shape).astype(np.float32).astype(np.float64)
+    return c, y
+
+
+def _with_k(og, k):
+    """The same oracle geometry with the sparse approximation of order k."""
+    return oracle.Geometry(og.n, og.ell_max, og.inner, og.outer, og.nj, og.nk, og.n_seg, og.frame,
+                           n_sub=og.n_sub, step=og.step, seg_span=og.seg_span, joff=og.joff, koff=og.koff,
+                           model=og.model, basis=og.basis, dirs=og.dirs, width=og.width, sparse_k=k)
+
+
+def _half_circle():
+    g = tiny()
+    return oracle.Geometry((9, 11, 10), 2, g.inner, g.outer, 12, 10, 6, synth.lab_frame(), seg_span=np.pi)
+
+
+def _nn():
+    g = small(ell_max=0)
+    return oracle.Geometry(g.n, 0, g.inner, g.outer, g.nj, g.nk, 8, synth.lab_frame(), basis="nn",
+                           dirs=synth.truncated_icosahedron_dirs())
+
+
+CASES = {
+    "tiny_k1": (lambda: tiny(), 1),
+    "tiny_offsets_step_k2": (lambda: tiny(offsets=True, step=0.8), 2),
+    "small_l4_k3": (lambda: small(ell_max=4), 3),
+    "small_l8_seg16_k4": (lambda: small(ell_max=8, n_seg=16), 4),
+    "small_l8_dense": (lambda: small(ell_max=8), 45),        # k = C: the exact map, fused
+    "small_l12_seg16_k6": (lambda: small(ell_max=12, n_seg=16), 6),
+    "half_circle_k2": (_half_circle, 2),                       # no antipodal fold: 6 distinct segments
+    "steep_k3": (lambda: steep(), 3),                          # global-memory gather inside the fused kernel
+    "degenerate_k2": (lambda: degenerate(), 2),
+    "c1_k4": (lambda: workload("c1"), 4),
+    "nn_k3_exact": (_nn, 3),                                   # nearest neighbour: n_sub nonzeros, kept exactly
+    "nn_k1": (_nn, 1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fused_forward_and_adjoint_parity(name):
+    make, k = CASES[name]
+    og = _with_k(make(), k)
+    c, y = _inputs(og, 11)
+    print(f"[sparse] {name}: n={og.n} C={og.n_coeff} S={og.n_proj} k={k}", flush=True)
+    P = gpu_projector(og, sparse_k=k)
+    assert P.batch == 0  # no mapped volumes in the workspace
+    Bt = P.basis_matrix()
+    assert np.abs(Bt - og.B()).max() <= 1e-13
+    ref = oracle.project(og, c)
+    got = _np(P.forward(_t(c)))
+    print(name, "fused forward rel-L2", rel_l2(got, ref), "rel-max", rel_max(got, ref))
+    assert rel_l2(got, ref) <= TOL
+    assert rel_max(got, ref) <= 10 * TOL
+    refa = oracle.adjoint(og, y)
+    gota = _np(P.adjoint(_t(y)))
+    print(name, "adjoint rel-L2", rel_l2(gota, refa))
+    assert rel_l2(gota, refa) <= TOL
+    assert rel_max(gota, refa) <= 10 * TOL
+
+
+def test_exact_when_nothing_is_dropped():
+    """k = C and the nearest-neighbour basis at k = n_sub reproduce the exact operator."""
+    for og, k in ((small(ell_max=4), 15), (_nn(), 3)):
+        c, _ = _inputs(og, 12)
+        ref = oracle.project(og, c)  # exact constants
+        P = gpu_projector(og, sparse_k=k)
+        got = _np(P.forward(_t(c)))
+        assert rel_l2(got, ref) <= TOL
+        Pd = gpu_projector(og)  # two-pass forward with the exact constants
+        assert rel_l2(got, _np(Pd.forward(_t(c)))) <= TOL
+
+
+def test_loss_grad_and_adjoint_identity():
+    og = _with_k(small(ell_max=8, n_seg=16), 3)
+    c, data = _inputs(og, 13)
+    rng = np.random.default_rng(14)
+    w = rng.uniform(0.5, 1.5, og.data_shape).astype(np.float32).astype(np.float64)
+    loss, grad, resid = oracle.loss_grad(og, c, data, w, 1e-3)
+    P = gpu_projector(og, sparse_k=3)
+    l_g, g_g, r_g = P.loss_grad(_t(c), _t(data), _t(w), 1e-3)
+    assert abs(float(l_g.item()) - loss) <= TOL * loss
+    assert rel_l2(_np(g_g), grad) <= TOL
+    assert rel_l2(_np(r_g), resid) <= TOL
+    # <A x, y> = <x, A^T y> with the fused forward and the backprojection
+    ct, yt = _t(c), _t(data)
+    I, g = P.forward(ct), P.adjoint(yt)
+    lhs = float((I.double() * yt.double()).sum())
+    rhs = float((ct.double() * g.double()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * float(I.double().norm()) * float(yt.double().norm())
+
+
+def test_lbfgs_iterates_match_the_oracle():
+    og = _with_k(workload("c1"), 3)
+    rng = np.random.default_rng(15)
+    c_true = rng.standard_normal(og.vol_shape)
+    data = oracle.project(og, c_true).astype(np.float32).astype(np.float64)
+    c_ref, it, hist, _ = oracle.lbfgs(og, np.zeros(og.vol_shape), data, None, 1e-3, m=10, max_iter=10)
+    from paper_2504_16446_amd.projector import LBFGS
+    P = gpu_projector(og, sparse_k=3)
+    solver = LBFGS(P, m=10)
+    c = torch.zeros(P.vol_shape, device=DEV)
+    solver.init(c, _t(data), None, 1e-3)
+    n_done, h = solver.run(10)
+    assert n_done == it == 10
+    print("sparse L-BFGS c rel-L2", rel_l2(_np(c), c_ref))
+    assert rel_l2(_np(c), c_ref) <= 1e-4
+    assert np.abs(h[:, 0] / hist[:, 0] - 1).max() <= 1e-5
+
+
+def test_mode_switches_and_errors():
+    og = small(ell_max=4)
+    c, _ = _inputs(og, 16)
+    P = gpu_projector(og)          # two-pass, mapped volumes in the workspace
+    ref = _np(P.forward(_t(c)))
+    call("tt_set_sparse_map", P._h, 2)
+    og2 = _with_k(og, 2)
+    assert rel_l2(_np(P.forward(_t(c))), oracle.project(og2, c)) <= TOL
+    call("tt_set_sparse_map", P._h, 0)  # back to the exact constants and the two-pass forward
+    assert rel_l2(_np(P.forward(_t(c))), ref) <= 1e-7
+    assert np.abs(P.basis_matrix() - og.B()).max() <= 1e-13
+    with pytest.raises(TTError) as e:
+        call("tt_set_sparse_map", P._h, -1)
+    assert e.value.code == -1
+    call("tt_set_map_precision", P._h, 1)
+    with pytest.raises(TTError) as e:  # bf16 tier
+        call("tt_set_sparse_map", P._h, 2)
+    assert e.value.code == -6
+    call("tt_set_map_precision", P._h, 0)
+    call("tt_set_projector", P._h, 1)
+    with pytest.raises(TTError) as e:  # Joseph's method
+        call("tt_set_sparse_map", P._h, 2)
+    assert e.value.code == -6
+    call("tt_set_projector", P._h, 0)
+    # a workspace without mapped volumes serves only the fused forward
+    Ps = gpu_projector(og, sparse_k=2)
+    call("tt_set_sparse_map", Ps._h, 0)
+    with pytest.raises(TTError) as e:
+        Ps.forward(_t(c))
+    assert e.value.code == -1
+    call("tt_set_sparse_map", Ps._h, 3)
+    for fn in ("tt_set_projector", "tt_set_map_precision"):  # Joseph's method, bf16 tier
+        with pytest.raises(TTError) as e:
+            call(fn, Ps._h, 1)
+        assert e.value.code == -6
+
+
+def test_full_size_sampled_parity_256():
+    """The fused forward at 256^3 / 400 projections / 16 segments (k = 2):
+    sampled rays against the oracle, adjoint identity over the whole operator."""
+    w = synth.WORKLOADS["c5"]
+    k = 2
+    print(f"[sparse] fullsize c5 k={k}", flush=True)
+    from paper_2504_16446_amd.projector import Projector
+    P = Projector.from_workload(w, device=DEV, sparse_k=k)
+    og = oracle.Geometry.from_workload(w, sparse_k=k)
+    rng = np.random.default_rng(78)
+    c = rng.standard_normal(P.vol_shape, dtype=np.float32)
+    ct = torch.from_numpy(c).to(DEV)
+    I = P.forward(ct)
+    sjk = np.stack([rng.integers(0, w.n_proj, 128), rng.integers(0, w.nj, 128), rng.integers(0, w.nk, 128)], 1)
+    ref = oracle.project_rays(og, c, sjk)
+    got = I[sjk[:, 0], sjk[:, 1], sjk[:, 2]].cpu().numpy()
+    e_f = rel_l2(got, ref)
+    yt = torch.randn(P.data_shape, device=DEV, generator=torch.Generator(device=DEV).manual_seed(5))
+    g = P.adjoint(yt)
+    lhs = float((I.double() * yt.double()).sum())
+    rhs = float((ct.double() * g.double()).sum())
+    gap = abs(lhs - rhs) / (float(I.double().norm()) * float(yt.double().norm()))
+    print(f"[sparse] fullsize c5: forward rays rel-L2 {e_f:.2e}, identity gap {gap:.2e}")
+    assert e_f <= 1e-5
+    assert gap <= 1e-6
