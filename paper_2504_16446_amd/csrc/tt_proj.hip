@@ -603,8 +603,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
             const int B0 = (int)floor(fma((double)A0, rB, kb)) - 1, Z0 = (int)floor(fma((double)A0, rZ, kz)) - 1;
             __syncthreads();  // the previous slab's gathers are done
             if constexpr (FUSED) {
-                // work item (box voxel e, segment u = thread mod UP), VS voxels per pass
-                constexpr int VS = 256 / UP;
+                // work item (box voxel e, segment u = thread mod UP), VS voxels per
+                // pass; EF items per thread have their loads in flight together
+                // (an item outside the volume reads c's first voxel and stores 0)
+                constexpr int VS = 256 / UP, EF = 4;
                 const int u = threadIdx.x & (UP - 1);
                 float *boxf = reinterpret_cast<float *>(box) + (long long)(u >> 2) * nbox * 4 + (u & 3);
                 const int2 *tu = tab + u * kk;
@@ -612,30 +614,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                 int pl = v0 / plane, ib = (v0 - pl * plane) / EZ, iz = v0 - pl * plane - ib * EZ;
                 const int t_pl = VS / plane, t_r = VS - t_pl * plane, t_ib = t_r / EZ, t_iz = t_r - t_ib * EZ;
                 const int nA = A == 0 ? nx : ny, nB = A == 0 ? ny : nx;
-                for (int e = v0; e < nbox; e += VS) {
-                    const int a = A0 + pl - 1, bq = B0 + ib - 1, z = Z0 + iz - 1;
-                    float v = 0.0f;
-                    if (u < U && (unsigned)a < (unsigned)nA && (unsigned)bq < (unsigned)nB && (unsigned)z < (unsigned)nz) {
+                for (int e0 = v0; e0 < nbox; e0 += VS * EF) {
+                    const float *src[EF];
+                    bool ok[EF];
+#pragma unroll
+                    for (int i = 0; i < EF; ++i) {
+                        const int a = A0 + pl - 1, bq = B0 + ib - 1, z = Z0 + iz - 1;
+                        ok[i] = u < U && e0 + VS * i < nbox && (unsigned)a < (unsigned)nA &&
+                                (unsigned)bq < (unsigned)nB && (unsigned)z < (unsigned)nz;
                         const int x = A == 0 ? a : bq, y = A == 0 ? bq : a;
-                        const float *src = M + ((long long)(x * ny + y) * nz + z) * C;
-#pragma unroll 4
-                        for (int t = 0; t < kk; ++t) {
-                            const int2 te = tu[t];
-                            v = fmaf(__int_as_float(te.y), src[te.x], v);
+                        src[i] = M + (ok[i] ? ((long long)(x * ny + y) * nz + z) * C : 0LL);
+                        pl += t_pl;
+                        ib += t_ib;
+                        iz += t_iz;
+                        if (iz >= EZ) {
+                            iz -= EZ;
+                            ++ib;
+                        }
+                        if (ib >= EB) {
+                            ib -= EB;
+                            ++pl;
                         }
                     }
-                    boxf[e * 4] = v;
-                    pl += t_pl;
-                    ib += t_ib;
-                    iz += t_iz;
-                    if (iz >= EZ) {
-                        iz -= EZ;
-                        ++ib;
+                    float v[EF];
+#pragma unroll
+                    for (int i = 0; i < EF; ++i) v[i] = 0.0f;
+#pragma unroll 2
+                    for (int t = 0; t < kk; ++t) {
+                        const int2 te = tu[t];
+                        const float wt = __int_as_float(te.y);
+#pragma unroll
+                        for (int i = 0; i < EF; ++i) v[i] = fmaf(wt, src[i][te.x], v[i]);
                     }
-                    if (ib >= EB) {
-                        ib -= EB;
-                        ++pl;
-                    }
+#pragma unroll
+                    for (int i = 0; i < EF; ++i)
+                        if (e0 + VS * i < nbox) boxf[(e0 + VS * i) * 4] = ok[i] ? v[i] : 0.0f;
                 }
             } else {
             const f4 *src0 = reinterpret_cast<const f4 *>(Mp) + ((long long)A0 * sA + (long long)B0 * sB + Z0) * Q;
