@@ -45,7 +45,7 @@ struct tt_ctx {
     int2 *d_sp = nullptr;       // [S][Up][sparse_k] sparse map (basis index, constant bits)
     float *d_Bu = nullptr;      // [bu_rows][Cp]: row s*Up + u, zero padded
     float *d_Bsw = nullptr;     // Bu in MFMA lane order (16-row tiles), for the forward map
-    uint16_t *d_Bsw16 = nullptr; // bf16 Bu in MFMA lane order (16-row tiles, k blocks of 16), forward
+    uint16_t *d_Bsw16 = nullptr; // bf16 Bu in MFMA lane order (16-row tiles, 32-coefficient steps), forward
     uint16_t *d_BuT16 = nullptr; // bf16 [S][Cp][16]: B^T with u padded to 16, adjoint
     int pb = 0;                 // projections per forward batch (0: no workspace attached)
     long long vol_pad = 0;
@@ -134,15 +134,24 @@ static void build_tables(const tt_ctx *c, Tables &t)
         for (int u = 0; u < d.U; ++u)
             for (int i = 0; i < d.C; ++i)
                 t.bu[((size_t)s * d.Up + u) * d.Cp + i] = (float)c->B[((size_t)s * d.nseg + u) * d.C + i];
-    const int KB = d.Cp / 16;
+    // row tile rt (16 Cp values): 32-coefficient steps kp, lane l, eight values
+    // bu[16 rt + l % 16][32 kp + 8 (l / 16) + q]; then, for Cp / 16 odd, the last
+    // 16 coefficients as four values bu[16 rt + l % 16][32 KP + 4 (l / 16) + q]
+    const int KP = d.Cp / 32;
     t.bsw16.assign(t.bu.size(), 0);
     t.but16.assign((size_t)S * d.Cp * 16, 0);
-    for (int rt = 0; rt < bu_rows / 16; ++rt)
-        for (int kb = 0; kb < KB; ++kb)
-            for (int l = 0; l < 64; ++l)
+    for (int rt = 0; rt < bu_rows / 16; ++rt) {
+        const size_t base = (size_t)rt * 16 * d.Cp;
+        for (int l = 0; l < 64; ++l) {
+            const float *row = &t.bu[((size_t)rt * 16 + l % 16) * d.Cp];
+            for (int kp = 0; kp < KP; ++kp)
+                for (int q = 0; q < 8; ++q)
+                    t.bsw16[base + ((size_t)kp * 64 + l) * 8 + q] = to_bf16(row[32 * kp + 8 * (l / 16) + q]);
+            if (d.Cp & 16)
                 for (int q = 0; q < 4; ++q)
-                    t.bsw16[(((size_t)rt * KB + kb) * 64 + l) * 4 + q] =
-                        to_bf16(t.bu[((size_t)rt * 16 + l % 16) * d.Cp + 16 * kb + 4 * (l / 16) + q]);
+                    t.bsw16[base + (size_t)KP * 512 + l * 4 + q] = to_bf16(row[32 * KP + 4 * (l / 16) + q]);
+        }
+    }
     for (int s = 0; s < S; ++s)
         for (int i = 0; i < d.Cp; ++i)
             for (int u = 0; u < d.Up; ++u)

@@ -18,12 +18,19 @@ namespace tt {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));    // eight bf16 bit patterns
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
-__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c)
+// gfx950 v_mfma_f32_16x16x32_bf16: D[16x16] += A[16x32] B[32x16].  Lane l
+// supplies row (A) / column (B) l % 16 and eight consecutive k of the group
+// l / 16; D as for the 16x16x16 forms (lane holds rows 4 (l / 16) + r of
+// column l % 16).  A and B take the same k order, so the per-lane k
+// assignment inside a group does not change the sum.
+__device__ __forceinline__ f4 mfma_bf16(s8 a, s8 b, f4 c)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                   0);
 }
 
 __device__ __forceinline__ u16 f2bf(float x)
@@ -48,7 +55,7 @@ enum { EPI_RELU_BF16 = 0, EPI_BIAS_F32 = 1, EPI_MASK_BF16 = 2 };
 // (two 16-row tiles) and all CO/16 column tiles.
 // ---------------------------------------------------------------------------
 template <int CI, int CO, int EPI>
-__global__ __launch_bounds__(256) void k_conv(const u16 *__restrict__ x, const s4 *__restrict__ wsw,
+__global__ __launch_bounds__(256) void k_conv(const u16 *__restrict__ x, const s8 *__restrict__ wsw,
                                               const float *__restrict__ bias, const u16 *__restrict__ mask,
                                               void *__restrict__ y, int X, int Y, int Z)
 {
@@ -79,7 +86,7 @@ __global__ __launch_bounds__(256) void k_conv(const u16 *__restrict__ x, const s
     }
     __syncthreads();
 
-    constexpr int NT = CO / 16, CB = CI / 16;
+    constexpr int NT = CO / 16, CB = CI / 32;
     f4 acc[2][NT];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -99,12 +106,12 @@ __global__ __launch_bounds__(256) void k_conv(const u16 *__restrict__ x, const s
         const int toff = (dx * HY + dy) * HZ + dz;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            s4 bv[NT];
+            s8 bv[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) bv[nt] = wsw[((tap * CB + cb) * NT + nt) * 64 + lane];
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
-                const s4 av = *reinterpret_cast<const s4 *>(halo + (hp[mt] + toff) * LD + cb * 16 + 4 * kq);
+                const s8 av = *reinterpret_cast<const s8 *>(halo + (hp[mt] + toff) * LD + cb * 32 + 8 * kq);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_bf16(av, bv[nt], acc[mt][nt]);
             }
@@ -202,13 +209,13 @@ __global__ __launch_bounds__(256) void k_wgrad(const u16 *__restrict__ x, const 
         __syncthreads();
         // gw[ci][co] += sum_v xs[ci][v] gs[co][v]: M = CI, N = CO, K = 128 voxels
 #pragma unroll
-        for (int ks = 0; ks < TV / 16; ++ks) {
+        for (int ks = 0; ks < TV / 32; ++ks) {
 #pragma unroll
             for (int i = 0; i < TPW; ++i) {
                 const int tile = wave * TPW + i;
                 const int mt = tile / NT, nt = tile % NT;
-                const s4 av = *reinterpret_cast<const s4 *>(xs + (mt * 16 + (lane & 15)) * LDV + ks * 16 + 4 * kq);
-                const s4 bv = *reinterpret_cast<const s4 *>(gs + (nt * 16 + (lane & 15)) * LDV + ks * 16 + 4 * kq);
+                const s8 av = *reinterpret_cast<const s8 *>(xs + (mt * 16 + (lane & 15)) * LDV + ks * 32 + 8 * kq);
+                const s8 bv = *reinterpret_cast<const s8 *>(gs + (nt * 16 + (lane & 15)) * LDV + ks * 32 + 8 * kq);
                 acc[i] = mfma_bf16(av, bv, acc[i]);
             }
         }
@@ -265,35 +272,31 @@ __global__ __launch_bounds__(64) void k_bias_reduce(const float *__restrict__ pa
 }
 
 // MFMA-ordered bf16 copies of w[27][ci][co]: forward (B[k = ci][n = co]) and
-// dgrad (w'[d][co][ci] = w[26 - d][ci][co], B[k = co][n = ci]).
-__global__ __launch_bounds__(256) void k_swizzle(const float *__restrict__ w, int CI, int CO, s4 *__restrict__ wf,
-                                                 s4 *__restrict__ wd)
+// dgrad (w'[d][co][ci] = w[26 - d][ci][co], B[k = co][n = ci]), eight k per lane.
+__global__ __launch_bounds__(256) void k_swizzle(const float *__restrict__ w, int CI, int CO, s8 *__restrict__ wf,
+                                                 s8 *__restrict__ wd)
 {
-    const int total = 27 * (CI / 16) * (CO / 16) * 64;
+    const int total = 27 * (CI / 32) * (CO / 16) * 64;  // = 27 (CO / 32) (CI / 16) 64
     for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
         const int l = e % 64;
         int r = e / 64;
-        // forward: e = ((tap * CB + cb) * NT + nt) * 64 + l with CB = CI/16, NT = CO/16
+        // forward: e = ((tap * CB + cb) * NT + nt) * 64 + l with CB = CI/32, NT = CO/16
         {
-            const int nt = r % (CO / 16), cb = (r / (CO / 16)) % (CI / 16), tap = r / ((CO / 16) * (CI / 16));
-            s4 v;
-            const int co = nt * 16 + l % 16, ci0 = cb * 16 + 4 * (l / 16);
-            v.x = (short)f2bf(w[((long long)tap * CI + ci0 + 0) * CO + co]);
-            v.y = (short)f2bf(w[((long long)tap * CI + ci0 + 1) * CO + co]);
-            v.z = (short)f2bf(w[((long long)tap * CI + ci0 + 2) * CO + co]);
-            v.w = (short)f2bf(w[((long long)tap * CI + ci0 + 3) * CO + co]);
+            const int nt = r % (CO / 16), cb = (r / (CO / 16)) % (CI / 32), tap = r / ((CO / 16) * (CI / 32));
+            const int co = nt * 16 + l % 16, ci0 = cb * 32 + 8 * (l / 16);
+            s8 v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = (short)f2bf(w[((long long)tap * CI + ci0 + q) * CO + co]);
             wf[e] = v;
         }
-        // dgrad: input channels CO, output channels CI: e = ((tap * (CO/16) + cb) * (CI/16) + nt) * 64 + l
+        // dgrad: input channels CO, output channels CI: e = ((tap * (CO/32) + cb) * (CI/16) + nt) * 64 + l
         {
-            const int nt = r % (CI / 16), cb = (r / (CI / 16)) % (CO / 16), tap = r / ((CI / 16) * (CO / 16));
+            const int nt = r % (CI / 16), cb = (r / (CI / 16)) % (CO / 32), tap = r / ((CI / 16) * (CO / 32));
             const int src = 26 - tap;
-            const int ci = nt * 16 + l % 16, co0 = cb * 16 + 4 * (l / 16);
-            s4 v;
-            v.x = (short)f2bf(w[((long long)src * CI + ci) * CO + co0 + 0]);
-            v.y = (short)f2bf(w[((long long)src * CI + ci) * CO + co0 + 1]);
-            v.z = (short)f2bf(w[((long long)src * CI + ci) * CO + co0 + 2]);
-            v.w = (short)f2bf(w[((long long)src * CI + ci) * CO + co0 + 3]);
+            const int ci = nt * 16 + l % 16, co0 = cb * 32 + 8 * (l / 16);
+            s8 v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = (short)f2bf(w[((long long)src * CI + ci) * CO + co0 + q]);
             wd[e] = v;
         }
     }
@@ -440,7 +443,7 @@ hipError_t conv_t(const u16 *x, const void *wsw, const float *bias, const u16 *m
                   hipStream_t st)
 {
     const int nb = N * ((X + TX - 1) / TX) * ((Y + TY - 1) / TY) * ((Z + TZ - 1) / TZ);
-    hipLaunchKernelGGL((k_conv<CI, CO, EPI>), dim3(nb), dim3(256), 0, st, x, reinterpret_cast<const s4 *>(wsw), bias,
+    hipLaunchKernelGGL((k_conv<CI, CO, EPI>), dim3(nb), dim3(256), 0, st, x, reinterpret_cast<const s8 *>(wsw), bias,
                        mask, y, X, Y, Z);
     return hipGetLastError();
 }
@@ -513,9 +516,9 @@ hipError_t net_wgrad(int ci, int co, const uint16_t *x, const uint16_t *gy, int 
 
 hipError_t net_swizzle(const float *w, int ci, int co, void *wf, void *wd, hipStream_t st)
 {
-    const int total = 27 * (ci / 16) * (co / 16) * 64;
-    hipLaunchKernelGGL(k_swizzle, dim3((total + 255) / 256), dim3(256), 0, st, w, ci, co, reinterpret_cast<s4 *>(wf),
-                       reinterpret_cast<s4 *>(wd));
+    const int total = 27 * (ci / 32) * (co / 16) * 64;
+    hipLaunchKernelGGL(k_swizzle, dim3((total + 255) / 256), dim3(256), 0, st, w, ci, co, reinterpret_cast<s8 *>(wf),
+                       reinterpret_cast<s8 *>(wd));
     return hipGetLastError();
 }
 

@@ -40,6 +40,16 @@ __device__ __forceinline__ f4 mfma16x16x16bf16(s4 a, s4 b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// gfx950 bf16 MFMA 16x16x32: lane l supplies A[l % 16][8 (l / 16) + q] and
+// B[8 (l / 16) + q][l % 16], q = 0..7; D as above.
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4 mfma16x16x32bf16(s8 a, s8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                   0);
+}
+
 // float -> bf16 bit pattern, round to nearest even (finite inputs).
 __device__ __forceinline__ short f2bf(float x)
 {
@@ -282,18 +292,22 @@ hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bsw, int 
 
 // ---------------------------------------------------------------------------
 // map, bf16 tier: c is rounded to bf16 while it is staged in LDS, B comes as
-// bf16 in MFMA lane order (Bsw16[(row_tile * Cp/16 + kb) * 64 + lane] holds
-// Bu[16 row_tile + lane % 16][16 kb + 4 (lane / 16) + q], q = 0..3), products
-// accumulate in fp32.  Same tiling as the fp32 kernel.
+// bf16 in MFMA lane order, products accumulate in fp32.  K = Cp runs in
+// 32-coefficient steps on the 16x16x32 instruction and, when Cp / 16 is odd,
+// a last 16-coefficient step on the 16x16x16 one.  Row tile rt of Bsw16
+// (16 Cp shorts at rt * 16 Cp) holds for step kp < Cp / 32 and lane l the
+// eight values Bu[16 rt + l % 16][32 kp + 8 (l / 16) + q] at (kp * 64 + l) * 8,
+// then for the odd step the four values Bu[16 rt + l % 16][32 (Cp / 32) +
+// 4 (l / 16) + q] at (Cp / 32) * 512 + l * 4.  Same tiling as the fp32 kernel.
 // ---------------------------------------------------------------------------
 template <int UP>
-__global__ __launch_bounds__(256) void k_map_bf16(const float *__restrict__ c, const s4 *__restrict__ Bsw16,
+__global__ __launch_bounds__(256) void k_map_bf16(const float *__restrict__ c, const short *__restrict__ Bsw16,
                                                   int V, int C, int Cp, int ny, int nz, int s0, int np,
                                                   long long vol_pad, float *__restrict__ M)
 {
-    extern __shared__ short cb[];  // [64][Cp + 4] bf16, row = voxel
+    extern __shared__ short cb[];  // [64][Cp + 8] bf16, row = voxel (16-byte rows)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ld = Cp + 4;
+    const int ld = Cp + 8;
     const int v0 = blockIdx.x * 64;
     const int nv = min(64, V - v0);
     const float *cg = c + (long long)v0 * C;
@@ -307,7 +321,7 @@ __global__ __launch_bounds__(256) void k_map_bf16(const float *__restrict__ c, c
     }
     __syncthreads();
 
-    const int KB = Cp / 16;
+    const int KP = Cp / 32;
     const int rt0 = (s0 * UP) / 16 + blockIdx.y * 16 + wave * 4;
     const int kq = lane >> 4;
     f4 acc[4][4];
@@ -315,13 +329,26 @@ __global__ __launch_bounds__(256) void k_map_bf16(const float *__restrict__ c, c
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 0; kb < KB; ++kb) {
-        s4 a[4];
+    for (int kp = 0; kp < KP; ++kp) {
+        s8 a[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a[mt] = Bsw16[((long long)(rt0 + mt) * KB + kb) * 64 + lane];
+        for (int mt = 0; mt < 4; ++mt)
+            a[mt] = *reinterpret_cast<const s8 *>(Bsw16 + (long long)(rt0 + mt) * 16 * Cp + (kp * 64 + lane) * 8);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            const s4 b = *reinterpret_cast<const s4 *>(cb + (nt * 16 + (lane & 15)) * ld + kb * 16 + 4 * kq);
+            const s8 b = *reinterpret_cast<const s8 *>(cb + (nt * 16 + (lane & 15)) * ld + kp * 32 + 8 * kq);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma16x16x32bf16(a[mt], b, acc[nt][mt]);
+        }
+    }
+    if (Cp & 16) {
+        s4 a[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            a[mt] = *reinterpret_cast<const s4 *>(Bsw16 + (long long)(rt0 + mt) * 16 * Cp + KP * 512 + lane * 4);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const s4 b = *reinterpret_cast<const s4 *>(cb + (nt * 16 + (lane & 15)) * ld + KP * 32 + 4 * kq);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) acc[nt][mt] = mfma16x16x16bf16(a[mt], b, acc[nt][mt]);
         }
@@ -347,8 +374,8 @@ static hipError_t map_bf16_t(const Dims &d, const float *c, const uint16_t *Bsw1
     const int V = d.nx * d.ny * d.nz;
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     dim3 grid((V + 63) / 64, (np * UP + 255) / 256);
-    size_t lds = (size_t)64 * (d.Cp + 4) * sizeof(short);
-    hipLaunchKernelGGL(k_map_bf16<UP>, grid, dim3(256), lds, st, c, reinterpret_cast<const s4 *>(Bsw16), V, d.C,
+    size_t lds = (size_t)64 * (d.Cp + 8) * sizeof(short);
+    hipLaunchKernelGGL(k_map_bf16<UP>, grid, dim3(256), lds, st, c, reinterpret_cast<const short *>(Bsw16), V, d.C,
                        d.Cp, d.ny, d.nz, s0, np, vol_pad, M);
     return hipGetLastError();
 }

@@ -134,18 +134,81 @@ def synthesize(w: synth.Workload, seeds, device, log_every=256):
     return Xs, Ts, kap
 
 
-def train(w: synth.Workload, n_phantoms=4096, epochs=20, batch=8, lr=1e-3, device="cuda:0", seed=0):
+def tiles_meeting_ball(n, radius, T=TILE, overlap=OVERLAP):
+    """Origins of the inference tiles whose box meets the support ball
+    (radius about the volume centre, voxel-centre coordinates)."""
+    orig = [tile_origins(m, T, overlap) for m in n]
+    keep = []
+    for ox in orig[0]:
+        for oy in orig[1]:
+            for oz in orig[2]:
+                d2 = 0.0
+                for o, m in zip((ox, oy, oz), n):
+                    lo, hi = o - (m - 1) / 2.0, o + T - 1 - (m - 1) / 2.0
+                    d2 += max(lo, 0.0, -hi) ** 2
+                if d2 <= radius * radius:
+                    keep.append((ox, oy, oz))
+    return keep
+
+
+def synthesize_tiles(w: synth.Workload, seeds, tiles_per_phantom, device, seed=0):
+    """Training tiles cut from whole phantoms of a large workload, as inference sees them.
+
+    Each seeded multi-bundle phantom of workload w is projected with w's
+    geometry (noise as w states) and backprojected; tiles_per_phantom of the
+    48^3 inference tiles that meet the support ball are drawn at random, and
+    the raw backprojection (first 28 channels) and the true coefficients are
+    copied out of them.  Returns (inputs, targets, kappa) like synthesize."""
+    dev = torch.device(device)
+    P = Projector.from_workload(w, device=dev)
+    kap = kappa(P, w.radius)
+    keep = tiles_meeting_ball(w.n, w.radius)
+    rng = np.random.default_rng(seed)
+    n = len(seeds) * tiles_per_phantom
+    Xs = torch.empty((n, TILE, TILE, TILE, NET_CH), device=dev)
+    Ts = torch.empty((n, TILE, TILE, TILE, NET_CH), device=dev)
+    I = torch.empty(P.data_shape, device=dev)
+    g = torch.empty(P.vol_shape, device=dev)
+    k = 0
+    for i, sd in enumerate(seeds):
+        c = bundle_phantom(w, int(sd), dev)
+        P.forward(c, out=I)
+        if w.noise > 0:
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(int(sd) + 100000)
+            I.add_(torch.randn(I.shape, generator=gen, device=dev), alpha=w.noise * float(I.abs().max()))
+        P.adjoint(I, out=g)
+        for t in rng.choice(len(keep), tiles_per_phantom, replace=False):
+            ox, oy, oz = keep[t]
+            Xs[k].copy_(g[ox:ox + TILE, oy:oy + TILE, oz:oz + TILE, :NET_CH])
+            Ts[k].copy_(c[ox:ox + TILE, oy:oy + TILE, oz:oz + TILE, :NET_CH])
+            k += 1
+        del c
+        _log("synthesised tiles", phantoms=i + 1, of=len(seeds), tiles=k)
+    del P, I, g
+    torch.cuda.empty_cache()
+    return Xs, Ts, kap
+
+
+def train(w: synth.Workload, n_phantoms=4096, epochs=20, batch=8, lr=1e-3, device="cuda:0", seed=0,
+          tiles_per_phantom=0, seed0=0):
+    """Train on whole 48^3 phantoms of w (tiles_per_phantom = 0, seeds 0..n-1) or on
+    tiles of larger phantoms of w (seeds seed0..seed0+n-1, see synthesize_tiles)."""
     dev = torch.device(device)
     t0 = time.time()
-    Xs, Ts, kap = synthesize(w, np.arange(n_phantoms), dev)
-    _log("training set ready", seconds=round(time.time() - t0, 2), kappa=kap)
+    if tiles_per_phantom > 0:
+        Xs, Ts, kap = synthesize_tiles(w, seed0 + np.arange(n_phantoms), tiles_per_phantom, dev, seed=seed)
+    else:
+        Xs, Ts, kap = synthesize(w, seed0 + np.arange(n_phantoms), dev)
+    n_phantoms = Xs.shape[0]
+    _log("training set ready", seconds=round(time.time() - t0, 2), kappa=kap, samples=n_phantoms)
     model = net.WarmStartNet(dev, seed=seed)
     model.set_input_statistics(Xs, pre=1.0 / kap)
     Xb = model.prepare_input(Xs, pre=1.0 / kap)  # bf16 [n, X, Y, Z, 32]
     del Xs
     torch.cuda.empty_cache()
     rng = np.random.default_rng(seed + 1)
-    nvox = batch * w.n_vox
+    nvox = batch * int(np.prod(Ts.shape[1:4]))
     history = []
     for ep in range(epochs):
         perm = rng.permutation(n_phantoms)
@@ -346,6 +409,11 @@ def main(argv=None):
     a.add_argument("--epochs", type=int, default=20)
     a.add_argument("--batch", type=int, default=8)
     a.add_argument("--lr", type=float, default=1e-3)
+    a.add_argument("--workload", default="c4",
+                   help="geometry and phantom generator of the training data (c4: whole 48^3 phantoms)")
+    a.add_argument("--tiles-per-phantom", type=int, default=0,
+                   help="> 0: train on this many random inference tiles of each (larger) phantom")
+    a.add_argument("--seed0", type=int, default=0, help="first phantom seed")
     b = sub.add_parser("holdout")
     b.add_argument("--weights", default=DEFAULT_WEIGHTS)
     b.add_argument("--count", type=int, default=16)
@@ -357,10 +425,13 @@ def main(argv=None):
     c.add_argument("--max-iter", type=int, default=2000)
     args = ap.parse_args(argv)
     if args.cmd == "train":
-        w = synth.WORKLOADS["c4"]
-        model, hist, kap = train(w, args.phantoms, args.epochs, args.batch, args.lr)
-        save(model, args.out, {"workload": "c4", "phantoms": args.phantoms, "epochs": args.epochs,
-                               "batch": args.batch, "lr": args.lr, "kappa_c4": kap, "sampled_mse": hist})
+        w = synth.WORKLOADS[args.workload]
+        model, hist, kap = train(w, args.phantoms, args.epochs, args.batch, args.lr,
+                                 tiles_per_phantom=args.tiles_per_phantom, seed0=args.seed0)
+        save(model, args.out, {"workload": args.workload, "phantoms": args.phantoms, "epochs": args.epochs,
+                               "tiles_per_phantom": args.tiles_per_phantom, "seed0": args.seed0,
+                               "batch": args.batch, "lr": args.lr, f"kappa_{args.workload}": kap,
+                               "sampled_mse": hist})
         _log("saved", path=args.out)
     elif args.cmd == "holdout":
         model = load(args.weights, "cuda:0")
