@@ -73,6 +73,10 @@ def kernel_roof(kind, w, n_unique, samples, launches_per_step, avg_s):
         flops = 2.0 * n_unique * C * V * per_launch_proj
         return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "algorithmic_flops_per_launch": flops, "count": "2 U C per voxel and projection"}
+    if kind == "fused":  # sparse fused forward: read the volume per projection, write the images
+        nbytes = per_launch_proj * (4.0 * C * V + img)
+        return {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "algorithmic_bytes_per_launch": nbytes, "count": "4 C V + 4 nj nk n_seg per projection"}
     if kind == "march":  # read the batch's mapped volumes, write its images
         nbytes = per_launch_proj * (4.0 * n_unique * V + img)
         return {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -393,6 +397,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the derived-quantity, Joseph and regulariser measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sparse-k", type=int, default=0,
+                    help="time the steps with the sparse fused forward keeping k basis constants per segment")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -423,12 +429,17 @@ def main():
         del src, dst
 
     P = Projector.from_workload(w, device=dev)
+    if args.sparse_k > 0:  # data from the exact operator, steps with the sparse fused forward
+        P_exact, P = P, Projector.from_workload(w, device=dev, sparse_k=args.sparse_k)
     samples = P.ray_samples()
     forward_batch = P.batch
     work_bytes = P.work_bytes
     c_true_np = phantom.coefficients(w)
     c_true = torch.from_numpy(c_true_np).to(dev)
-    data = P.forward(c_true)
+    data = (P_exact if args.sparse_k > 0 else P).forward(c_true)
+    if args.sparse_k > 0:
+        del P_exact
+        torch.cuda.empty_cache()
     if w.noise > 0:
         sigma = w.noise * float(data.abs().max())
         noise = torch.from_numpy(synth.noise(P.data_shape, w.seed_noise).astype(np.float32)).to(dev)
@@ -469,7 +480,7 @@ def main():
             kernels[k] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
                           "avg_launch_ms": ms / n}
     roofs = {}
-    for k in ("map", "march", "backproject"):
+    for k in ("map", "march", "fused", "backproject"):
         if k in kernels:
             r = kernel_roof(k, w, P.n_unique, samples, kernels[k]["launches_per_step"],
                             kernels[k]["avg_launch_ms"] * 1e-3)
@@ -529,6 +540,12 @@ def main():
     regs = None if args.no_extras else regulariser_bench(dev)
     print("[bench] sparse fused forward ...", file=sys.stderr, flush=True)
     sparse = None if args.no_extras else sparse_bench(w, dev)
+    print("[bench] warm-start network layers ...", file=sys.stderr, flush=True)
+    if args.no_extras:
+        netb = None
+    else:
+        from paper_2504_16446_amd import net as _net
+        netb = _net.bench(dev)
     if sparse is not None:
         sparse["two_pass_ms_forward"] = sum(kernels[k]["ms_per_step"] for k in ("map", "march") if k in kernels)
         sparse["two_pass_workspace_bytes"] = work_bytes
@@ -539,6 +556,7 @@ def main():
         "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n[0]}^3 voxels, ell_max {w.ell_max} ({w.n_coeff} coeffs), "
+                               + (f"sparse fused map k={args.sparse_k}, " if args.sparse_k > 0 else "") +
                                f"{w.n_proj} projections, {w.nj}x{w.nk} px x {w.n_seg} segments, "
                                f"{w.phantom} phantom, noise {w.noise}; "
                                f"step = one L-BFGS iteration (m=10, mu={w.mu})",
@@ -554,6 +572,7 @@ def main():
         "joseph": joseph,
         "regularisers": regs,
         "sparse_fused": sparse,
+        "network": netb,
     }
     print(json.dumps(line), flush=True)
 

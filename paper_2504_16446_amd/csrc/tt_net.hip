@@ -149,16 +149,36 @@ __global__ __launch_bounds__(256) void k_conv(const u16 *__restrict__ x, const s
 // Weight gradient, split over K (voxels): block (tap, chunk) accumulates
 // gw[tap] over the voxel tiles t = chunk, chunk + nchunks, ... and writes its
 // CI x CO partial; a second kernel sums the partials in chunk order.
-// Tiles are staged channel-major in LDS so both MFMA operands read 4
-// consecutive voxels of one channel.
+// Tiles are staged channel-major in LDS so both MFMA operands read 8
+// consecutive voxels of one channel.  Staging item (row, octet): the 8
+// voxels of one z-row of the tile (contiguous in the tile's voxel order) and
+// 8 channels; the thread loads the 8 voxels' 16-byte channel octets,
+// transposes the 8 x 8 block in registers and writes 8 rows of 16 bytes.
+// The next tile's loads are issued before the current tile's MFMAs.
 // ---------------------------------------------------------------------------
+struct Oct8 {
+    uint4 v[8];
+};
+
+// w[q] = the q-th channel of the 8 voxels in r.v[0..7], as 8 packed bf16
+__device__ __forceinline__ uint4 oct_column(const Oct8 &r, int q)
+{
+    unsigned h[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const unsigned word = (q >> 1) == 0 ? r.v[i].x : (q >> 1) == 1 ? r.v[i].y : (q >> 1) == 2 ? r.v[i].z : r.v[i].w;
+        h[i] = (q & 1) ? (word >> 16) : (word & 0xffffu);
+    }
+    return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
 template <int CI, int CO>
 __global__ __launch_bounds__(256) void k_wgrad(const u16 *__restrict__ x, const u16 *__restrict__ gy, int N, int X,
                                                int Y, int Z, int nchunks, float *__restrict__ part)
 {
-    constexpr int LDV = TV + 8;  // padded voxel stride (bf16)
-    __shared__ u16 xs[CI * LDV];
-    __shared__ u16 gs[CO * LDV];
+    constexpr int LDV = TV + 8;  // padded voxel stride (bf16; 16-byte rows)
+    __shared__ __attribute__((aligned(16))) u16 xs[CI * LDV];
+    __shared__ __attribute__((aligned(16))) u16 gs[CO * LDV];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tap = blockIdx.x / nchunks, chunk = blockIdx.x % nchunks;
     const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
@@ -167,11 +187,23 @@ __global__ __launch_bounds__(256) void k_wgrad(const u16 *__restrict__ x, const 
     const long long vol = (long long)X * Y * Z;
     constexpr int MT = CI / 16, NT = CO / 16;
     constexpr int TPW = MT * NT / 4;  // output tiles per wave
-    f4 acc[TPW];
+    constexpr int ROWS = TX * TY;     // z-rows of TZ = 8 voxels per tile
+    constexpr int XI = ROWS * (CI / 8), GI = ROWS * (CO / 8);  // staging items of x and gy
+    static_assert(TZ == 8 && XI + GI <= 256, "one staging item per thread");
+    // this thread's staging item: x rows first, then gy rows
+    const bool is_x = tid < XI, has_item = tid < XI + GI;
+    const int it = is_x ? tid : tid - XI;
+    const int row = it % ROWS, oct = it / ROWS;
+    const int rtx = row / TY, rty = row % TY;
+    const int cstride = is_x ? CI : CO;
+    const u16 *src = is_x ? x : gy;
+    const int sx = is_x ? dx : 0, sy = is_x ? dy : 0, sz = is_x ? dz : 0;
+    u16 *dst = (is_x ? xs : gs) + oct * 8 * LDV + row * TZ;
+
+    auto load = [&](int t, Oct8 &r) {
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-    const int kq = lane >> 4;
-    for (int t = chunk; t < ntiles; t += nchunks) {
+        for (int i = 0; i < 8; ++i) r.v[i] = make_uint4(0, 0, 0, 0);
+        if (!has_item || t >= ntiles) return;
         int b = t;
         const int bz = b % nbz;
         b /= nbz;
@@ -179,34 +211,31 @@ __global__ __launch_bounds__(256) void k_wgrad(const u16 *__restrict__ x, const 
         b /= nby;
         const int bx = b % nbx;
         const int n = b / nbx;
-        __syncthreads();
-        // stage x shifted by the tap and gy, both channel-major
-        for (int e = tid; e < TV * (CI / 8); e += 256) {
-            const int vt = e / (CI / 8), ch = e % (CI / 8);
-            const int tz = vt % TZ, ty = (vt / TZ) % TY, tx = vt / (TZ * TY);
-            const int ox = bx * TX + tx, oy = by * TY + ty, oz = bz * TZ + tz;
-            const int gx = ox + dx, gyy = oy + dy, gz = oz + dz;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (ox < X && oy < Y && oz < Z && gx >= 0 && gx < X && gyy >= 0 && gyy < Y && gz >= 0 && gz < Z)
-                val = *reinterpret_cast<const uint4 *>(x + ((long long)n * vol + ((long long)gx * Y + gyy) * Z + gz) * CI +
-                                                       ch * 8);
-            const u16 *h = reinterpret_cast<const u16 *>(&val);
+        const int ox = bx * TX + rtx, oy = by * TY + rty;
+        const int gx = ox + sx, gyy = oy + sy;
+        if (ox >= X || oy >= Y || gx < 0 || gx >= X || gyy < 0 || gyy >= Y) return;
+        const u16 *p = src + ((long long)n * vol + ((long long)gx * Y + gyy) * Z) * cstride + oct * 8;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) xs[(ch * 8 + q) * LDV + vt] = h[q];
+        for (int i = 0; i < 8; ++i) {
+            const int oz = bz * TZ + i, gz = oz + sz;
+            if (oz < Z && gz >= 0 && gz < Z) r.v[i] = *reinterpret_cast<const uint4 *>(p + (long long)gz * cstride);
         }
-        for (int e = tid; e < TV * (CO / 8); e += 256) {
-            const int vt = e / (CO / 8), ch = e % (CO / 8);
-            const int tz = vt % TZ, ty = (vt / TZ) % TY, tx = vt / (TZ * TY);
-            const int ox = bx * TX + tx, oy = by * TY + ty, oz = bz * TZ + tz;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (ox < X && oy < Y && oz < Z)
-                val = *reinterpret_cast<const uint4 *>(gy + ((long long)n * vol + ((long long)ox * Y + oy) * Z + oz) * CO +
-                                                       ch * 8);
-            const u16 *h = reinterpret_cast<const u16 *>(&val);
+    };
+
+    f4 acc[TPW];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) gs[(ch * 8 + q) * LDV + vt] = h[q];
+    for (int i = 0; i < TPW; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+    const int kq = lane >> 4;
+    Oct8 cur;
+    load(chunk, cur);
+    for (int t = chunk; t < ntiles; t += nchunks) {
+        __syncthreads();  // the previous tile's MFMA reads are done
+        if (has_item) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) *reinterpret_cast<uint4 *>(dst + q * LDV) = oct_column(cur, q);
         }
         __syncthreads();
+        load(t + nchunks, cur);  // next tile in flight during the MFMAs
         // gw[ci][co] += sum_v xs[ci][v] gs[co][v]: M = CI, N = CO, K = 128 voxels
 #pragma unroll
         for (int ks = 0; ks < TV / 32; ++ks) {
@@ -261,14 +290,21 @@ __global__ __launch_bounds__(256) void k_bias_partial(const u16 *__restrict__ gy
     }
 }
 
-// bias gradient, stage 2: gb[co] = sum over blocks (fixed order)
-__global__ __launch_bounds__(64) void k_bias_reduce(const float *__restrict__ partial, int nblk, int CO, float *gb)
+// bias gradient, stage 2: gb[co] = sum over blocks, one block per channel: thread t
+// adds partials t, t + 256, ... in order, then a fixed-shape tree in LDS
+__global__ __launch_bounds__(256) void k_bias_reduce(const float *__restrict__ partial, int nblk, int CO, float *gb)
 {
-    const int c = threadIdx.x;
-    if (c >= CO) return;
+    __shared__ float sh[256];
+    const int c = blockIdx.x, t = threadIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += partial[(long long)b * CO + c];
-    gb[c] = s;
+    for (int b = t; b < nblk; b += 256) s += partial[(long long)b * CO + c];
+    sh[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) gb[c] = sh[0];
 }
 
 // MFMA-ordered bf16 copies of w[27][ci][co]: forward (B[k = ci][n = co]) and
@@ -510,7 +546,7 @@ hipError_t net_wgrad(int ci, int co, const uint16_t *x, const uint16_t *gy, int 
     if (e != hipSuccess || !gb) return e;
     float *bp = work + (size_t)27 * nch * ci * co;
     hipLaunchKernelGGL(k_bias_partial, dim3(kBiasBlocks), dim3(256), 0, st, gy, (long long)N * X * Y * Z, co, bp);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(1), dim3(64), 0, st, bp, kBiasBlocks, co, gb);
+    hipLaunchKernelGGL(k_bias_reduce, dim3(co), dim3(256), 0, st, bp, kBiasBlocks, co, gb);
     return hipGetLastError();
 }
 

@@ -190,3 +190,60 @@ class WarmStartNet:
             l.swizzle()
         self.in_shift.copy_(d["in_shift"].to(self.device))
         self.in_scale.copy_(d["in_scale"].to(self.device))
+
+
+def layer_flops(n_vox):
+    """Multiply-add flops of the forward of every layer at the padded channel counts the
+    kernels run (2 x 27 x ci x co per voxel)."""
+    return [2.0 * 27 * _pad(CHANNELS[i]) * _pad(CHANNELS[i + 1]) * n_vox for i in range(6)]
+
+
+def bench(device="cuda:0", batch=8, T=48, reps=5):
+    """Event-timed forward, input-gradient and weight-gradient launches of every layer and
+    the whole training step at batch x T^3 voxels, with the flops of each at the padded
+    channel counts (TFLOP/s against the bf16 dense MFMA peak of 2500 TFLOP/s)."""
+    dev = torch.device(device)
+    model = WarmStartNet(dev, seed=0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    x = pack_bf16(torch.randn((batch, T, T, T, CHANNELS[0]), device=dev, generator=g), 32)
+    target = torch.randn((batch, T, T, T, CHANNELS[-1]), device=dev, generator=g)
+    st = torch.cuda.current_stream(dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record(st)
+        for _ in range(reps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    y, acts = model.forward(x, keep=True)
+    work = model._ensure_work(batch, T, T, T)
+    flops = layer_flops(batch * T ** 3)
+    rows = []
+    for i, l in enumerate(model.layers):
+        epi = BIAS_F32 if i == 5 else RELU_BF16
+        gy = bf16_empty((batch, T, T, T, l.co), dev)
+        gy.copy_(pack_bf16(torch.randn((batch, T, T, T, l.co), device=dev, generator=g), l.co))
+        f_ms = timed(lambda: l.forward(acts[i], epi))
+        d_ms = timed(lambda: l.backward_input(gy, acts[i])) if i > 0 else None
+        w_ms = timed(lambda: l.backward_weights(acts[i], gy, work))
+        rows.append({"layer": i, "ci": l.ci, "co": l.co, "forward_ms": f_ms, "forward_TFLOPs": flops[i] / f_ms / 1e9,
+                     "dgrad_ms": d_ms, "dgrad_TFLOPs": flops[i] / d_ms / 1e9 if d_ms else None,
+                     "wgrad_ms": w_ms, "wgrad_TFLOPs": flops[i] / w_ms / 1e9})
+    step_ms = timed(lambda: model.train_step(x, target))
+    total = 3 * sum(flops) - flops[0]  # no input gradient for the first layer
+    return {"batch": batch, "tile": T, "layers": rows, "train_step_ms": step_ms,
+            "train_step_TFLOPs": total / step_ms / 1e9, "peak_TFLOPs": 2500.0,
+            "frac": total / step_ms / 1e9 / 2500.0}
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    print(json.dumps(bench(reps=int(sys.argv[1]) if len(sys.argv) > 1 else 5)))
