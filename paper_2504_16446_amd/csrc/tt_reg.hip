@@ -87,9 +87,138 @@ __global__ __launch_bounds__(256) void k_laplacian(const float *__restrict__ in,
     }
 }
 
+// Sliding-window form for 16-byte aligned rows (nz C a multiple of 4): a
+// block owns LY rows (y) x LZ floats (a float4-aligned segment of the
+// contiguous z-C row) and marches along x through a range of planes.  The
+// planes x - 1, x, x + 1 of its own elements stay in registers (each element
+// is read from memory once per range, plus one plane at each end); plane x
+// is staged in LDS with its y-halo rows (y0 - 1, y0 + LY) and z-halo (C
+// floats on either side of the segment) for the four in-plane neighbours,
+// zero outside the volume.  The next plane's loads are issued before the
+// current plane is staged.
+constexpr int kLY = 8, kLZ = 512;            // tile: 8 rows x 512 floats = 1024 float4
+constexpr int kLF4 = kLY * kLZ / 4 / 256;    // float4 per thread
+
+template <bool ACC>
+__global__ __launch_bounds__(256) void k_laplacian_x(const float *__restrict__ in, int nx, int ny, int nz, int C,
+                                                     int xr, float *__restrict__ out, float scale,
+                                                     double *__restrict__ partials)
+{
+    __shared__ double ws[4];
+    extern __shared__ float pl[];  // (kLY + 2) rows of kLZ + 2 CP floats, interior at column CP
+    const long long R = (long long)nz * C;  // row length (floats), a multiple of 4
+    const int nzs = (int)((R + kLZ - 1) / kLZ), nyt = (ny + kLY - 1) / kLY;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int zs = lb % nzs, yt = (lb / nzs) % nyt, xg = lb / (nzs * nyt);
+    const int y0 = yt * kLY;
+    const long long e0 = (long long)zs * kLZ;
+    const int x0 = xg * xr, x1 = min(nx, x0 + xr);
+    const int CP = (C + 3) & ~3;  // halo width rounded to float4: every row and the interior 16-byte aligned
+    const int L = kLZ + 2 * CP;
+    const long long sx = (long long)ny * R;
+    // this thread's float4s: element q -> (row, column) of the tile
+    int rr[kLF4], cc[kLF4];
+    bool ok[kLF4];
+#pragma unroll
+    for (int q = 0; q < kLF4; ++q) {
+        const int f = threadIdx.x + 256 * q;
+        rr[q] = f / (kLZ / 4);
+        cc[q] = 4 * (f % (kLZ / 4));
+        ok[q] = y0 + rr[q] < ny && e0 + cc[q] < R;
+    }
+    auto load_plane = [&](int x, f4r v[kLF4]) {
+#pragma unroll
+        for (int q = 0; q < kLF4; ++q) {
+            v[q] = f4r{0.f, 0.f, 0.f, 0.f};
+            if (x >= 0 && x < nx && ok[q])
+                v[q] = *reinterpret_cast<const f4r *>(in + x * sx + (long long)(y0 + rr[q]) * R + e0 + cc[q]);
+        }
+    };
+    f4r vp[kLF4], vc[kLF4], vn[kLF4];
+    load_plane(x0 - 1, vp);
+    load_plane(x0, vc);
+    double ss = 0.0;
+    for (int x = x0; x < x1; ++x) {
+        load_plane(x + 1, vn);
+        __syncthreads();  // the previous plane's LDS reads are done
+        // interior
+#pragma unroll
+        for (int q = 0; q < kLF4; ++q) *reinterpret_cast<f4r *>(pl + (rr[q] + 1) * L + CP + cc[q]) = vc[q];
+        // y-halo rows: columns [0, kLZ) of rows y0 - 1 and y0 + kLY
+        const float *px = in + x * sx;
+        for (int i = threadIdx.x; i < 2 * (kLZ / 4); i += 256) {
+            const int side = i / (kLZ / 4), col = 4 * (i % (kLZ / 4));
+            const int y = side ? y0 + kLY : y0 - 1;
+            f4r v = f4r{0.f, 0.f, 0.f, 0.f};
+            if (y >= 0 && y < ny && e0 + col < R) v = *reinterpret_cast<const f4r *>(px + (long long)y * R + e0 + col);
+            *reinterpret_cast<f4r *>(pl + (side ? kLY + 1 : 0) * L + CP + col) = v;
+        }
+        // z-halo: C floats on either side of the segment, interior rows
+        for (int i = threadIdx.x; i < 2 * kLY * C; i += 256) {
+            const int row = i / (2 * C), j = i % (2 * C);
+            const long long e = j < C ? e0 - C + j : e0 + kLZ + (j - C);
+            const int y = y0 + row;
+            float v = 0.0f;
+            if (y < ny && e >= 0 && e < R) v = px[(long long)y * R + e];
+            pl[(row + 1) * L + (j < C ? CP - C + j : CP + kLZ + (j - C))] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kLF4; ++q) {
+            if (!ok[q]) continue;
+            const float *p = pl + (rr[q] + 1) * L + CP + cc[q];
+            f4r a = vp[q] + vn[q] - 6.0f * vc[q] + *reinterpret_cast<const f4r *>(p - L) +
+                    *reinterpret_cast<const f4r *>(p + L);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) a[l] += p[l - C] + p[l + C];
+            f4r *o = reinterpret_cast<f4r *>(out + x * sx + (long long)(y0 + rr[q]) * R + e0 + cc[q]);
+            if (ACC) {
+                *o = scale * a + *o;
+            } else {
+                *o = a;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) ss += (double)a[l] * (double)a[l];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kLF4; ++q) {
+            vp[q] = vc[q];
+            vc[q] = vn[q];
+        }
+    }
+    if (!ACC && partials) {
+        const double t = block_sum(ss, ws);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
 hipError_t launch_laplacian_reg(const float *c, int nx, int ny, int nz, int C, double lam, float *work, float *grad,
                                 double *value, double *partials, hipStream_t st)
 {
+    const long long R = (long long)nz * C;
+    const bool aligned16 = ((reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(work) |
+                             reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
+    if (aligned16 && (R & 3) == 0 && C <= kLapMaxC) {
+        // x ranges: enough blocks to fill the chip (>= 2048), at most kReduceBlocks
+        const long long cols = ((R + kLZ - 1) / kLZ) * ((ny + kLY - 1) / kLY);
+        if (cols <= kReduceBlocks) {
+            int nxg = (int)std::max(1LL, std::min<long long>(nx, (2048 + cols - 1) / cols));
+            nxg = (int)std::min<long long>(nxg, kReduceBlocks / cols);
+            const int xr = (nx + nxg - 1) / nxg;
+            nxg = (nx + xr - 1) / xr;
+            const int blocks = (int)(cols * nxg);
+            const size_t lds = sizeof(float) * (size_t)(kLY + 2) * (kLZ + 2 * ((C + 3) & ~3));
+            hipLaunchKernelGGL(k_laplacian_x<false>, dim3(blocks), dim3(256), lds, st, c, nx, ny, nz, C, xr, work,
+                               0.0f, value ? partials : nullptr);
+            if (value) {
+                hipError_t e = launch_sum_partials(partials, blocks, value, lam, 1, st);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(k_laplacian_x<true>, dim3(blocks), dim3(256), lds, st, work, nx, ny, nz, C, xr, grad,
+                               (float)(2.0 * lam), nullptr);
+            return hipGetLastError();
+        }
+    }
     const int zc = std::max(4, (kLapChunkFloats / C) & ~3);  // multiple of 4
     const long long chunks = (long long)nx * ny * ((nz + zc - 1) / zc);
     if (C > kLapMaxC) return hipErrorNotSupported;

@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-@pytest.mark.parametrize("shape", [(7, 9, 5, 15), (1, 3, 2, 6), (3, 4, 300, 45), (5, 3, 70, 45), (100, 100, 100, 45)])
+@pytest.mark.parametrize("shape", [(7, 9, 5, 15), (1, 3, 2, 6), (3, 4, 300, 45), (5, 3, 70, 45), (100, 100, 100, 45),
+                                   (37, 29, 41, 16), (6, 10, 64, 1)])
 def test_laplacian_reg_parity(shape):
     rng = np.random.default_rng(21)
     c = rng.standard_normal(shape).astype(np.float32)
