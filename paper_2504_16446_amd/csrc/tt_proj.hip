@@ -532,8 +532,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
     const int tab_f4 = FUSED ? (UP * kk * 8 + 15) / 16 : 0;
     f4 *box = lds + tab_f4;        // [Q][W + 1][eb][ez]
     const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
-    // (handing each XCD a contiguous range of tiles, so that neighbouring
-    // tiles' overlapping boxes share an L2, measured 5% slower at 256^3)
     const int lb = blockIdx.x;
     const int p = lb / (ntj * ntk), s = s0 + p;
     const int tj = (lb / ntk) % ntj, tk = lb % ntk;
