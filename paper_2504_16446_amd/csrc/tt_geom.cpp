@@ -270,7 +270,8 @@ int plan_slabs(std::vector<ProjFrame> &frames, int up, int lds_budget)
                 }
             }
             const int eb = (int)std::floor(hi[0] - lo[0]) + 5, ez = (int)std::floor(hi[1] - lo[1]) + 5;
-            const long long bytes = (long long)(W + 1) * eb * ez * up * (long long)sizeof(float);
+            // element arrays padded to 64 (the march copies whole waves of 64)
+            const long long bytes = (((long long)(W + 1) * eb * ez + 63) & ~63LL) * up * (long long)sizeof(float);
             if (bytes <= lds_budget) {
                 f.slab_w = W;
                 f.slab_eb = eb;

@@ -598,6 +598,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
             kz = fmin(kz, b00[2] + J * f.ej[2] + K * f.ek[2] + t * rZ);
         }
         const int plane = EB * EZ, nbox = (W + 1) * plane;
+        const int nbs = (nbox + 63) & ~63;  // LDS stride of one float4 component array of the box
         // M strides (in voxels) of the box axes A and B; z is contiguous
         const int sy = nz + 2, sx = (ny + 2) * sy;
         const int sA = A == 0 ? sx : sy, sB = A == 0 ? sy : sx;
@@ -635,7 +636,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                 // (an item outside the volume reads c's first voxel and stores 0)
                 constexpr int VS = 256 / UP, EF = 4;
                 const int u = threadIdx.x & (UP - 1);
-                float *boxf = reinterpret_cast<float *>(box) + (long long)(u >> 2) * nbox * 4 + (u & 3);
+                float *boxf = reinterpret_cast<float *>(box) + (long long)(u >> 2) * nbs * 4 + (u & 3);
                 const int2 *tu = tab + u * kk;
                 const int v0 = threadIdx.x / UP;
                 int pl = v0 / plane, ib = (v0 - pl * plane) / EZ, iz = v0 - pl * plane - ib * EZ;
@@ -678,46 +679,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                         if (e0 + VS * i < nbox) boxf[(e0 + VS * i) * 4] = ok[i] ? v[i] : 0.0f;
                 }
             } else {
+            // direct global -> LDS copies (gfx950 global_load_lds, 16 bytes a
+            // lane): wave w copies elements e = 256 i + 64 w + lane of every
+            // float4 component array, all in flight together; elements outside
+            // the padded volume and the tail up to the 64-element stride copy
+            // the zero border voxel at padded index 0
             const f4 *src0 = reinterpret_cast<const f4 *>(Mp) + ((long long)A0 * sA + (long long)B0 * sB + Z0) * Q;
-            constexpr int KB = 4;  // staged voxels per thread in flight
+            const f4 *zsrc = reinterpret_cast<const f4 *>(Mp);
+            const int wb = threadIdx.x & ~63, lane = threadIdx.x & 63;
             int pl = e_pl, ib = e_ib, iz = e_iz, off = e_pl * sA + e_ib * sB + e_iz;
-            for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * KB) {
-                f4 v[KB][Q];
+            for (int eb = wb; eb < nbox; eb += 256) {
+                const bool in = eb + lane < nbox && (unsigned)(A0 + pl) <= nAp && (unsigned)(B0 + ib) <= nBp &&
+                                (unsigned)(Z0 + iz) <= nZp;
+                const f4 *gsrc = in ? src0 + (long long)off * Q : zsrc;
 #pragma unroll
-                for (int kb = 0; kb < KB; ++kb) {
-                    const int e = e0 + 256 * kb;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) v[kb][q] = f4{0.f, 0.f, 0.f, 0.f};
-                    if (e < nbox && (unsigned)(A0 + pl) <= nAp && (unsigned)(B0 + ib) <= nBp &&
-                        (unsigned)(Z0 + iz) <= nZp) {
-#pragma unroll
-                        for (int q = 0; q < Q; ++q) v[kb][q] = src0[off * Q + q];
-                    }
-                    // advance by 256 elements
-                    pl += s_pl;
-                    ib += s_ib;
-                    iz += s_iz;
-                    off += s_off;
-                    if (iz >= EZ) {
-                        iz -= EZ;
-                        ++ib;
-                        off += cz_off;
-                    }
-                    if (ib >= EB) {
-                        ib -= EB;
-                        ++pl;
-                        off += cb_off;
-                    }
+                for (int q = 0; q < Q; ++q)
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(gsrc + q),
+                                                     (__attribute__((address_space(3))) void *)(box + q * nbs + eb),
+                                                     16, 0, 0);
+                // advance by 256 elements
+                pl += s_pl;
+                ib += s_ib;
+                iz += s_iz;
+                off += s_off;
+                if (iz >= EZ) {
+                    iz -= EZ;
+                    ++ib;
+                    off += cz_off;
                 }
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) {
-                    const int e = e0 + 256 * kb;
-                    if (e < nbox) {
-#pragma unroll
-                        for (int q = 0; q < Q; ++q) box[q * nbox + e] = v[kb][q];
-                    }
+                if (ib >= EB) {
+                    ib -= EB;
+                    ++pl;
+                    off += cb_off;
                 }
             }
+            __builtin_amdgcn_s_waitcnt(0);
             }
             __syncthreads();
             // samples of this slab: index position along A below A0 + W
@@ -746,7 +742,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                 for (int cc = 0; cc < 8; ++cc) {
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const f4 mv = box[q * nbox + base + off8[cc]];
+                        const f4 mv = box[q * nbs + base + off8[cc]];
                         acc[4 * q + 0] = fmaf(w[cc], mv.x, acc[4 * q + 0]);
                         acc[4 * q + 1] = fmaf(w[cc], mv.y, acc[4 * q + 1]);
                         acc[4 * q + 2] = fmaf(w[cc], mv.z, acc[4 * q + 2]);
