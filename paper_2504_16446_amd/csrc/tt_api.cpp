@@ -357,9 +357,10 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         return fail(TT_EUNSUPPORTED, "detector too large: nj * nk * " + std::to_string(d.Up / 4) +
                                          " must stay below 2^24 (float4 units of one projection)");
     }
-    // staged march LDS per 256-ray tile: 32 KiB for four unique segments, 64
-    // KiB for more (measured best of 32/48/64 KiB on 100^3 x 4 and 256^3 x 8)
-    d.march_lds = plan_slabs(c->frames, d.Up, (d.Up == 4 ? 32 : 64) * 1024);
+    // staged march LDS per 256-ray tile: 52 KiB for four unique segments (three
+    // blocks per CU), 76 KiB for more (two blocks per CU); measured best of
+    // 20-76 KiB on 100^3 x 4 and of 32-76 KiB on 128^3 and 256^3 x 8
+    d.march_lds = plan_slabs(c->frames, d.Up, (d.Up == 4 ? 52 : 76) * 1024);
     d.win_ok = backproject_window_fits(c->frames) ? 1 : 0;
     d.pw_lds = backproject_pw_lds(c->frames, d.Up, d.pw_wr, d.pw_wc);
 
