@@ -135,10 +135,17 @@ int tt_set_map_precision(tt_ctx *ctx, int precision);
  *     runs one fused kernel for all projections that forms the unique segment
  *     values sum_t B_{sc,i_t} c_{v,i_t} of each voxel while staging the
  *     coefficient volume for the ray sums (no mapped volumes in the
- *     workspace).  tt_adjoint, tt_loss_grad, the solver, tt_kappa and
- *     tt_basis_matrix use the same approximated constants, so the pair stays
- *     exactly adjoint.  The constants are rebuilt on the host and uploaded
- *     (synchronous; waits for the context's stream).
+ *     workspace).  When no projection keeps more than 8 basis functions over
+ *     its unique segments, tt_project first copies c channel-major into the
+ *     workspace (C x nx ny nz floats) and the staging reads only the kept
+ *     channels; otherwise it reads the coefficient records.  tt_adjoint,
+ *     tt_loss_grad, the solver, tt_kappa and tt_basis_matrix use the same
+ *     approximated constants, so the pair stays exactly adjoint.  The
+ *     constants are rebuilt on the host and uploaded (synchronous; waits for
+ *     the context's stream).  A call that changes the workspace layout
+ *     (between k = 0 and k >= 1, or across the channel-major threshold)
+ *     releases the attached workspace: attach one sized by tt_workspace_bytes
+ *     in the new mode before computing.
  * TT_EINVAL for k < 0; TT_EUNSUPPORTED for k >= 1 with Joseph's method or the
  * bf16 map tier (and tt_set_projector / tt_set_map_precision return
  * TT_EUNSUPPORTED for those while a sparse map is set). */
@@ -177,12 +184,12 @@ int tt_sizes(const tt_ctx *ctx, int64_t *out8);
  * (rounded to what the map kernel accepts; forward_batch = 1 gives the
  * smallest valid workspace, >= n_proj the whole set in one batch;
  * forward_batch <= 0 gives the workspace without mapped volumes, which serves
- * only the fused forward of tt_set_sparse_map).
+ * only the fused forward of tt_set_sparse_map; with a sparse map of at most 8
+ * kept basis functions per projection the workspace also holds a
+ * channel-major copy of c, nx ny nz C floats).
  * tt_set_workspace attaches caller memory (device, 256-byte aligned) and
  * picks the largest batch that fits; TT_EINVAL below the smallest size (with
- * a sparse map set, below the size without mapped volumes; tt_project then
- * returns TT_EINVAL if the sparse map is switched off again while the
- * attached workspace holds no mapped volume).  The
+ * a sparse map set, below the size without mapped volumes).  The
  * memory must stay allocated and untouched by the caller while attached; the
  * zero border is written once, on the context's stream.  Calls that compute
  * (tt_project, tt_adjoint, tt_loss_grad, the solver, tt_kappa,

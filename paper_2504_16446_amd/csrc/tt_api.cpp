@@ -43,6 +43,7 @@ struct tt_ctx {
     std::vector<double> B_exact;  // the exact constants (B differs under a sparse map)
     ProjFrame *d_frames = nullptr;
     int2 *d_sp = nullptr;       // [S][Up][sparse_k] sparse map (basis index, constant bits)
+    int *d_gtab = nullptr;      // [S][sparse_ng (Up + 1)] channel list and constants of the fused staging
     float *d_Bu = nullptr;      // [bu_rows][Cp]: row s*Up + u, zero padded
     float *d_Bsw = nullptr;     // Bu in MFMA lane order (16-row tiles), for the forward map
     uint16_t *d_Bsw16 = nullptr; // bf16 Bu in MFMA lane order (16-row tiles, 32-coefficient steps), forward
@@ -59,6 +60,7 @@ struct tt_ctx {
     float *d_yf = nullptr;      // [S][nj][nk][Up]
     float *d_resid = nullptr;   // [S][nj][nk][n_seg]
     float *d_M = nullptr;       // [pb][vol_pad][Up], zero border
+    float *d_cT = nullptr;      // [C][V] channel-major copy of c (fused sparse forward only)
     size_t table_bytes = 0;
     bool timing = false;
     struct Mark {
@@ -384,6 +386,7 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     const std::vector<float> &bu = t.bu, &bsw = t.bsw;
     const std::vector<uint16_t> &bsw16 = t.bsw16, &but16 = t.but16;
     const size_t sp_len = (size_t)S * d.Up * d.C;
+    const size_t gtab_len = (size_t)S * d.C * (d.Up + 1);
 
     auto cleanup = [&](int code, const std::string &msg) {
         tt_destroy(c);
@@ -394,9 +397,11 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
         hipMalloc(&c->d_Bsw, bsw.size() * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_Bsw16, bsw16.size() * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc(&c->d_BuT16, but16.size() * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&c->d_sp, sp_len * sizeof(int2)) != hipSuccess)
+        hipMalloc(&c->d_sp, sp_len * sizeof(int2)) != hipSuccess ||
+        hipMalloc(&c->d_gtab, gtab_len * sizeof(int)) != hipSuccess)
         return cleanup(TT_ENOMEM, "device allocation failed");
-    c->table_bytes = sizeof(ProjFrame) * S + bu.size() * 10 + but16.size() * 2 + sp_len * sizeof(int2);
+    c->table_bytes = sizeof(ProjFrame) * S + bu.size() * 10 + but16.size() * 2 + sp_len * sizeof(int2) +
+                     gtab_len * sizeof(int);
     if (hipMemcpy(c->d_frames, c->frames.data(), sizeof(ProjFrame) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bu, bu.data(), bu.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_Bsw, bsw.data(), bsw.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
@@ -419,6 +424,7 @@ void tt_destroy(tt_ctx *c)
     hipFree(c->d_Bsw16);
     hipFree(c->d_BuT16);
     hipFree(c->d_sp);
+    hipFree(c->d_gtab);
     delete c;
 }
 
@@ -461,6 +467,8 @@ int tt_set_sparse_map(tt_ctx *c, int k)
     if (k > 0 && c->precision == TT_MAP_BF16) return fail(TT_EUNSUPPORTED, "the sparse fused map runs in float32 only");
     const int kk = std::min(k, d.C);
     std::vector<int2> sp;
+    std::vector<int> gtab;
+    int ng = 0;
     if (k == 0) {
         c->B = c->B_exact;
     } else {
@@ -482,6 +490,30 @@ int tt_set_sparse_map(tt_ctx *c, int k)
                 for (int cs = u; cs < d.nseg; cs += d.U)
                     std::memcpy(&c->B[((size_t)s * d.nseg + cs) * d.C], sparse.data(), sizeof(double) * d.C);
             }
+        // channel lists of the fused staging: the basis functions any unique
+        // segment of the projection keeps, in increasing order, with their
+        // constants per segment (zero where a segment does not keep them)
+        std::vector<std::vector<int>> lists(d.S);
+        for (int s = 0; s < d.S; ++s) {
+            std::vector<char> used(d.C, 0);
+            for (int u = 0; u < d.U; ++u)
+                for (int t = 0; t < kk; ++t) used[sp[((size_t)s * d.Up + u) * kk + t].x] = 1;
+            for (int i = 0; i < d.C; ++i)
+                if (used[i]) lists[s].push_back(i);
+            ng = std::max(ng, (int)lists[s].size());
+        }
+        gtab.assign((size_t)d.S * ng * (d.Up + 1), 0);
+        for (int s = 0; s < d.S; ++s) {
+            int *row = &gtab[(size_t)s * ng * (d.Up + 1)];
+            for (size_t g = 0; g < lists[s].size(); ++g) {
+                row[g] = lists[s][g];
+                for (int u = 0; u < d.U; ++u) {
+                    const float w = (float)c->B[((size_t)s * d.nseg + u) * d.C + lists[s][g]];
+                    std::memcpy(&row[ng + g * d.Up + u], &w, 4);
+                }
+            }
+            // unused list slots keep channel 0 with zero constants
+        }
     }
     Tables t;
     build_tables(c, t);
@@ -491,7 +523,17 @@ int tt_set_sparse_map(tt_ctx *c, int k)
     TT_HIP(hipMemcpy(c->d_Bsw16, t.bsw16.data(), t.bsw16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     TT_HIP(hipMemcpy(c->d_BuT16, t.but16.data(), t.but16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     if (!sp.empty()) TT_HIP(hipMemcpy(c->d_sp, sp.data(), sp.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if (!gtab.empty()) TT_HIP(hipMemcpy(c->d_gtab, gtab.data(), gtab.size() * sizeof(int), hipMemcpyHostToDevice));
+    const bool was_fused = c->d.sparse_k > 0;
     c->d.sparse_k = k == 0 ? 0 : kk;
+    c->d.sparse_ng = ng;
+    const bool cm_changed = c->d.sparse_cm != (k > 0 && ng <= kFusedCmChannels ? 1 : 0);
+    c->d.sparse_cm = k > 0 && ng <= kFusedCmChannels ? 1 : 0;
+    if (was_fused != (k > 0) || cm_changed) {  // the workspace layout changes: the caller attaches a new one
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        c->pb = 0;
+    }
     return TT_OK;
 }
 
@@ -544,7 +586,7 @@ int tt_sizes(const tt_ctx *c, int64_t *out8)
 
 // Workspace layout for a forward batch of pb projections (pb = 0: no mapped volumes).
 struct WsLayout {
-    size_t part, yf, resid, M, total;
+    size_t part, yf, resid, cT, M, total;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static WsLayout ws_layout(const tt_ctx *c, int pb)
@@ -557,6 +599,8 @@ static WsLayout ws_layout(const tt_ctx *c, int pb)
     off += align256(sizeof(float) * (size_t)c->d.S * c->d.nj * c->d.nk * c->d.Up);
     L.resid = off;
     off += align256(sizeof(float) * (size_t)n_data(c));
+    L.cT = off;  // channel-major copy of c for the fused sparse forward
+    if (c->d.sparse_k > 0 && c->d.sparse_cm) off += align256(sizeof(float) * (size_t)n_coef(c));
     L.M = off;
     off += align256(c->per_proj * (size_t)pb);
     L.total = off;
@@ -584,11 +628,11 @@ static int need_ws(const tt_ctx *c)
 // or the library's static array (tt_loss_grad_noalloc, untimed: no events).
 struct Scratch {
     double *part;
-    float *yf, *resid, *M;
+    float *yf, *resid, *M, *cT;
     int pb;
     bool timed;
 };
-static Scratch attached(const tt_ctx *c) { return {c->d_part, c->d_yf, c->d_resid, c->d_M, c->pb, true}; }
+static Scratch attached(const tt_ctx *c) { return {c->d_part, c->d_yf, c->d_resid, c->d_M, c->d_cT, c->pb, true}; }
 
 int64_t tt_workspace_bytes(const tt_ctx *c, int forward_batch)
 {
@@ -621,6 +665,7 @@ int tt_set_workspace(tt_ctx *c, void *work, size_t bytes)
     c->d_yf = reinterpret_cast<float *>(c->ws + L.yf);
     c->d_resid = reinterpret_cast<float *>(c->ws + L.resid);
     c->d_M = reinterpret_cast<float *>(c->ws + L.M);
+    c->d_cT = reinterpret_cast<float *>(c->ws + L.cT);
     // the map writes only interior voxels: the border of every mapped volume stays zero
     if (pb > 0) TT_HIP(hipMemsetAsync(c->d_M, 0, c->per_proj * (size_t)pb, c->stream));
     return TT_OK;
@@ -692,7 +737,7 @@ static int project_sc(tt_ctx *c, const Scratch &sc, const float *cin, float *I)
         hipError_t e;
         {
             KTimer t(c, TT_K_FUSED, sc.timed);
-            e = launch_march_fused(c->d, c->d_frames, cin, c->d_sp, I, c->stream);
+            e = launch_march_fused(c->d, c->d_frames, cin, c->d_sp, c->d_gtab, sc.cT, I, c->stream);
         }
         if (e != hipSuccess) return fail(TT_EHIP, std::string("fused march: ") + hipGetErrorString(e));
         return TT_OK;
@@ -801,8 +846,10 @@ int tt_loss_grad_noalloc(tt_ctx *c, const float *cin, const float *data, const f
     // same layout as an attached workspace, the batch as large as the array allows
     WsLayout L = ws_layout(c, 0);
     if (resid) {  // the residual goes to the caller's buffer: no data-sized scratch
-        L.M = L.resid;
-        L.total = L.resid;
+        const size_t shift = L.cT - L.resid;
+        L.cT -= shift;
+        L.M -= shift;
+        L.total -= shift;
     }
     const size_t cap = kStaticScratchBytes;
     const long long fit = cap > L.total ? (long long)((cap - L.total) / c->per_proj) : 0;
@@ -818,6 +865,7 @@ int tt_loss_grad_noalloc(tt_ctx *c, const float *cin, const float *data, const f
     sc.yf = reinterpret_cast<float *>(base + L.yf);
     sc.resid = resid ? nullptr : reinterpret_cast<float *>(base + L.resid);
     sc.M = reinterpret_cast<float *>(base + L.M);
+    sc.cT = reinterpret_cast<float *>(base + L.cT);
     sc.pb = pb;
     sc.timed = false;
     // the map writes interior voxels only; the array holds whatever the last

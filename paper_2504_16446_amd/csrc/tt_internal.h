@@ -95,7 +95,15 @@ struct Dims {
                                // window rows / columns
     int sparse_k = 0;   // 0: exact basis constants, map + march; >= 1: kept basis functions per
                         //    (projection, segment) of the sparse map, fused forward
+    int sparse_ng = 0;  // fused forward: channels per projection's list (the most any projection uses)
+    int sparse_cm = 0;  // fused forward stages from a channel-major copy of c (few channels per projection)
 };
+
+// The fused forward stages from a channel-major copy of c when no projection
+// keeps more than this many basis functions over its unique segments, and
+// from the coefficient records c[v][0..C) otherwise (measured: with 8 or
+// fewer channels the per-channel arrays cost less than whole 4C-byte records).
+constexpr int kFusedCmChannels = 8;
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
 hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,
@@ -108,8 +116,12 @@ hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, 
 // Fused sparse forward: I[s][j][k][c] = step * ray sums over projection s of
 // m_u(v) = sum_t w_t c[v][i_t] with (i_t, w_t) = sp[s][u][t] (int2: basis index,
 // float bits), t < d.sparse_k, u = c mod U; all projections in one launch.
-hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp, float *I,
-                              hipStream_t st);
+// The staged voxels read the channel-major copy cT[i][v] (written first, V C
+// floats of caller workspace) through the per-projection channel list gtab[s] =
+// {ng channel indices, then ng x Up constants as float bits}; rays that gather
+// from global memory use sp and c.
+hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp,
+                              const int *gtab, float *cT, float *I, hipStream_t st);
 // yf[s][j][k][u] = scale * sum_{c: c mod U = u} y[s][j][k][c] (optionally
 // y = 2 w (Ip - data) with the loss partials, see launch_residual_fold).
 hipError_t launch_fold(const Dims &d, const float *y, float scale, float *yf, hipStream_t st);

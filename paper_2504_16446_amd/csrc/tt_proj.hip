@@ -524,12 +524,15 @@ template <int UP, bool FUSED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 && !FUSED) ? 5 : 1))) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
                                                int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
                                                float step, long long vol_pad, float *__restrict__ I,
-                                               const int2 *__restrict__ sp, int kk, int C)
+                                               const int2 *__restrict__ sp, int kk, int C,
+                                               const float *__restrict__ cT, const int *__restrict__ gtab, int ng)
 {
     constexpr int Q = UP / 4;      // float4 per staged voxel
-    extern __shared__ f4 lds[];    // FUSED: the map table int2[UP][kk], then the box
+    // FUSED: the map table int2[UP][kk] (global-memory gathers), the channel
+    // list int[ng] and its constants float[ng][UP] (staging), then the box
+    extern __shared__ f4 lds[];
     __shared__ int arange[2];
-    const int tab_f4 = FUSED ? (UP * kk * 8 + 15) / 16 : 0;
+    const int tab_f4 = FUSED ? (UP * kk * 8 + 15) / 16 + (ng * (UP + 1) * 4 + 15) / 16 : 0;
     f4 *box = lds + tab_f4;        // [Q][W + 1][eb][ez]
     const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
     const int lb = blockIdx.x;
@@ -541,9 +544,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
     const ProjFrame &f = frames[s];
     const float *Mp = FUSED ? M : M + (long long)p * vol_pad * UP;
     int2 *tab = reinterpret_cast<int2 *>(lds);
+    int *gch = reinterpret_cast<int *>(lds + (UP * kk * 8 + 15) / 16);  // [ng] channels, then [ng][UP] constants
+    const float *gw = reinterpret_cast<const float *>(gch + ng);
     if constexpr (FUSED) {
         const int2 *src = sp + (long long)s * UP * kk;
         for (int i = threadIdx.x; i < UP * kk; i += 256) tab[i] = src[i];
+        const int *gsrc = gtab + (long long)s * ng * (UP + 1);
+        for (int i = threadIdx.x; i < ng * (UP + 1); i += 256) gch[i] = gsrc[i];
         __syncthreads();
     }
     double b[3], ds[3];
@@ -631,6 +638,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
             const int B0 = (int)floor(fma((double)A0, rB, kb)) - 1, Z0 = (int)floor(fma((double)A0, rZ, kz)) - 1;
             __syncthreads();  // the previous slab's gathers are done
             if constexpr (FUSED) {
+              if (cT) {
+                // thread t stages box elements e = t + 256 i (the walk of the
+                // copying path), two at a time: the ng selected channels of each
+                // voxel come from the channel-major copy cT[i][voxel], so a wave's
+                // loads of one channel are 64 consecutive z voxels; the unique
+                // segment values m_u = sum_g w[g][u] cT[g] are written as Q float4s
+                const long long V = (long long)nx * ny * nz;
+                const int nA = A == 0 ? nx : ny, nB = A == 0 ? ny : nx;
+                int pl = e_pl, ib = e_ib, iz = e_iz;
+                auto voxel = [&](int e, long long &vox) {
+                    const int a = A0 + pl - 1, bq = B0 + ib - 1, z = Z0 + iz - 1;
+                    const bool in = e < nbox && (unsigned)a < (unsigned)nA && (unsigned)bq < (unsigned)nB &&
+                                    (unsigned)z < (unsigned)nz;
+                    const int x = A == 0 ? a : bq, y = A == 0 ? bq : a;
+                    vox = in ? ((long long)x * ny + y) * nz + z : 0LL;
+                    pl += s_pl;
+                    ib += s_ib;
+                    iz += s_iz;
+                    if (iz >= EZ) {
+                        iz -= EZ;
+                        ++ib;
+                    }
+                    if (ib >= EB) {
+                        ib -= EB;
+                        ++pl;
+                    }
+                    return in;
+                };
+                for (int e0 = threadIdx.x; e0 < nbox; e0 += 512) {
+                    long long v0, v1;
+                    const bool in0 = voxel(e0, v0), in1 = voxel(e0 + 256, v1);
+                    float m0[UP], m1[UP];
+#pragma unroll
+                    for (int u = 0; u < UP; ++u) m0[u] = m1[u] = 0.0f;
+                    for (int g = 0; g < ng; ++g) {
+                        const float *ch = cT + (long long)gch[g] * V;
+                        const float x0 = ch[v0], x1 = ch[v1];
+#pragma unroll
+                        for (int u = 0; u < UP; ++u) {
+                            const float wv = gw[g * UP + u];
+                            m0[u] = fmaf(wv, x0, m0[u]);
+                            m1[u] = fmaf(wv, x1, m1[u]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        box[q * nbs + e0] = in0 ? f4{m0[4 * q], m0[4 * q + 1], m0[4 * q + 2], m0[4 * q + 3]}
+                                                : f4{0.f, 0.f, 0.f, 0.f};
+                        if (e0 + 256 < nbox)
+                            box[q * nbs + e0 + 256] = in1 ? f4{m1[4 * q], m1[4 * q + 1], m1[4 * q + 2], m1[4 * q + 3]}
+                                                          : f4{0.f, 0.f, 0.f, 0.f};
+                    }
+                }
+              } else {
                 // work item (box voxel e, segment u = thread mod UP), VS voxels per
                 // pass; EF items per thread have their loads in flight together
                 // (an item outside the volume reads c's first voxel and stores 0)
@@ -678,6 +739,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                     for (int i = 0; i < EF; ++i)
                         if (e0 + VS * i < nbox) boxf[(e0 + VS * i) * 4] = ok[i] ? v[i] : 0.0f;
                 }
+              }
             } else {
             // direct global -> LDS copies (gfx950 global_load_lds, 16 bytes a
             // lane): wave w copies elements e = 256 i + 64 w + lane of every
@@ -852,29 +914,56 @@ static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_march<UP, false>), grid, dim3(kMarchTile * kMarchTile), d.march_lds, st, M, frames, s0,
-                       d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I, nullptr, 0, 0);
+                       d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I, nullptr, 0, 0, nullptr, nullptr, 0);
     return hipGetLastError();
 }
 
 template <int UP>
-static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp, float *I,
-                                hipStream_t st)
+static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp,
+                                const float *cT, const int *gtab, float *I, hipStream_t st)
 {
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * d.S);
-    const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + d.march_lds;
+    const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + (d.sparse_ng * (UP + 1) * 4 + 15) / 16 * 16 + d.march_lds;
     hipLaunchKernelGGL((k_march<UP, true>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx, d.ny,
-                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C);
+                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab, d.sparse_ng);
     return hipGetLastError();
 }
 
-hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp, float *I,
-                              hipStream_t st)
+// cT[i][v] = c[v][i]: 64 voxels per block step, staged in LDS (odd row stride)
+__global__ __launch_bounds__(256) void k_channel_major(const float *__restrict__ c, long long V, int C,
+                                                       float *__restrict__ cT)
+{
+    extern __shared__ float tile[];  // [64][C + 1]
+    const int ld = C + 1;
+    for (long long v0 = (long long)blockIdx.x * 64; v0 < V; v0 += (long long)gridDim.x * 64) {
+        const int nv = (int)min(64LL, V - v0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nv * C; e += 256) {
+            const int v = e / C, i = e - v * C;
+            tile[v * ld + i] = c[v0 * C + e];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * C; e += 256) {
+            const int i = e >> 6, v = e & 63;
+            if (v < nv) cT[(long long)i * V + v0 + v] = tile[v * ld + i];
+        }
+    }
+}
+
+hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp,
+                              const int *gtab, float *cT, float *I, hipStream_t st)
 {
     if (d.sparse_k < 1 || d.joseph) return hipErrorInvalidValue;
+    const long long V = (long long)d.nx * d.ny * d.nz;
+    if (d.sparse_cm)
+        hipLaunchKernelGGL(k_channel_major, dim3((unsigned)std::min<long long>((V + 63) / 64, 4096)), dim3(256),
+                           64 * (d.C + 1) * sizeof(float), st, c, V, d.C, cT);
+    else
+        cT = nullptr;  // stage from the coefficient records
     switch (d.Up) {
-    case 4: return march_fused_t<4>(d, frames, c, sp, I, st);
-    case 8: return march_fused_t<8>(d, frames, c, sp, I, st);
-    case 16: return march_fused_t<16>(d, frames, c, sp, I, st);
+    case 4: return march_fused_t<4>(d, frames, c, sp, cT, gtab, I, st);
+    case 8: return march_fused_t<8>(d, frames, c, sp, cT, gtab, I, st);
+    case 16: return march_fused_t<16>(d, frames, c, sp, cT, gtab, I, st);
     default: return hipErrorInvalidValue;
     }
 }

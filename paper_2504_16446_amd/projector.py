@@ -103,12 +103,23 @@ class Projector:
         call("tt_set_projector", self._h,
              _lib.TT_PROJ_JOSEPH if model == "joseph" else _lib.TT_PROJ_TRILINEAR)
         self.model = model
-        # sparse_k >= 1: the sparse fused forward (no mapped volumes in the workspace)
-        self.sparse_k = int(sparse_k)
-        call("tt_set_sparse_map", self._h, self.sparse_k)
-        # Workspace (device memory owned here, handed to the library): the
-        # forward maps `forward_batch` projections per pass; by default as many
-        # as fit a budget of 1/8 of the free device memory, clamped to [1, 24] GiB.
+        self.n = tuple(int(v) for v in n)
+        self.ell_max, self.n_proj = int(ell_max), g.n_proj
+        self.nj, self.nk, self.n_seg = int(nj), int(nk), int(n_seg)
+        self.precision = map_precision
+        self._ws = None
+        self.sparse_k = 0
+        self.set_sparse_map(int(sparse_k), forward_batch, workspace_budget)
+
+    def set_sparse_map(self, k: int, forward_batch=None, workspace_budget=None):
+        """Select the exact map (k = 0) or the sparse fused forward with k kept
+        basis constants per projection and segment, and attach a workspace for
+        that mode (device memory owned here, handed to the library).  The
+        two-pass forward maps `forward_batch` projections per pass; by default
+        as many as fit a budget of 1/8 of the free device memory, clamped to
+        [1, 24] GiB.  The fused forward needs no mapped volumes."""
+        call("tt_set_sparse_map", self._h, int(k))
+        self.sparse_k = int(k)
         sizes = (C.c_int64 * 8)()
         call("tt_sizes", self._h, sizes)
         per_proj = int(sizes[7])
@@ -119,17 +130,15 @@ class Projector:
                 free, _ = torch.cuda.mem_get_info(self.device)
                 workspace_budget = min(24 << 30, max(1 << 30, free // 8))
             forward_batch = max(1, int(workspace_budget) // per_proj)
-        nbytes = int(call("tt_workspace_bytes", self._h, int(min(forward_batch, g.n_proj))))
-        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        nbytes = int(call("tt_workspace_bytes", self._h, int(min(forward_batch, self.n_proj))))
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._bind_stream()
         call("tt_set_workspace", self._h, C.c_void_p(self._ws.data_ptr()), nbytes)
         call("tt_sizes", self._h, sizes)
-        self.n = tuple(int(v) for v in n)
-        self.ell_max, self.n_proj = int(ell_max), g.n_proj
-        self.nj, self.nk, self.n_seg = int(nj), int(nk), int(n_seg)
         self.n_coeff, self.n_unique, self.batch, self.work_bytes = (
             int(sizes[2]), int(sizes[3]), int(sizes[4]), int(sizes[5]))
-        self.precision = map_precision
 
     @classmethod
     def from_workload(cls, w: synth.Workload, **kw):

@@ -150,10 +150,18 @@ def test_mode_switches_and_errors():
     c, _ = _inputs(og, 16)
     P = gpu_projector(og)          # two-pass, mapped volumes in the workspace
     ref = _np(P.forward(_t(c)))
-    call("tt_set_sparse_map", P._h, 2)
+    call("tt_set_sparse_map", P._h, 2)  # the mode changes: the workspace is released
+    with pytest.raises(TTError) as e:
+        P.forward(_t(c))
+    assert e.value.code == -1
+    P.set_sparse_map(2)                 # re-attached for the fused forward
     og2 = _with_k(og, 2)
+    assert P.batch == 0
     assert rel_l2(_np(P.forward(_t(c))), oracle.project(og2, c)) <= TOL
-    call("tt_set_sparse_map", P._h, 0)  # back to the exact constants and the two-pass forward
+    P.set_sparse_map(3)                 # other k (staging layout and workspace may change)
+    assert rel_l2(_np(P.forward(_t(c))), oracle.project(_with_k(og, 3), c)) <= TOL
+    P.set_sparse_map(0)                 # back to the exact constants and the two-pass forward
+    assert P.batch > 0
     assert rel_l2(_np(P.forward(_t(c))), ref) <= 1e-7
     assert np.abs(P.basis_matrix() - og.B()).max() <= 1e-13
     with pytest.raises(TTError) as e:
@@ -169,17 +177,17 @@ def test_mode_switches_and_errors():
         call("tt_set_sparse_map", P._h, 2)
     assert e.value.code == -6
     call("tt_set_projector", P._h, 0)
-    # a workspace without mapped volumes serves only the fused forward
     Ps = gpu_projector(og, sparse_k=2)
-    call("tt_set_sparse_map", Ps._h, 0)
-    with pytest.raises(TTError) as e:
-        Ps.forward(_t(c))
-    assert e.value.code == -1
-    call("tt_set_sparse_map", Ps._h, 3)
     for fn in ("tt_set_projector", "tt_set_map_precision"):  # Joseph's method, bf16 tier
         with pytest.raises(TTError) as e:
             call(fn, Ps._h, 1)
         assert e.value.code == -6
+    # a workspace below the fused size (channel-major copy included) is refused
+    small_bytes = int(call("tt_workspace_bytes", Ps._h, 0)) - 4096
+    buf = torch.empty(small_bytes, dtype=torch.uint8, device=DEV)
+    with pytest.raises(TTError) as e:
+        call("tt_set_workspace", Ps._h, C.c_void_p(buf.data_ptr()), small_bytes)
+    assert e.value.code == -1
 
 
 def test_full_size_sampled_parity_256():
