@@ -411,18 +411,32 @@ hipError_t launch_map_bf16(const Dims &d, const float *c, const uint16_t *Bsw16,
 
 // Ray setup shared by both paths: index-space base point b and step ds of the
 // ray through pixel (j, k), and its sample range [n0, n1] (empty if n0 > n1).
+// Joseph's method (jos): the samples are the ray's cuts with the voxel-centre
+// planes of its dominant axis A, so the base point is moved to the cut with
+// plane A = 0 and the spacing is d / |d_A|: sample n lies on plane
+// n sign(d_A), and the same box constraints keep the planes 1..n_A and the
+// cuts whose in-plane coordinates stay inside (0, n + 1).
 __device__ __forceinline__ void ray_setup(const ProjFrame &f, int j, int k, int nx, int ny, int nz, float step,
-                                          double b[3], double ds[3], int &n0, int &n1)
+                                          double b[3], double ds[3], int &n0, int &n1, bool jos = false)
 {
     const double n3[3] = {(double)nx, (double)ny, (double)nz};
     double tlo = -1e300, thi = 1e300;
+    double scale = (double)step;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) b[a] = f.o[a] + j * f.ej[a] + k * f.ek[a] + 0.5 * (n3[a] + 1.0);
+    if (jos) {
+        const int A = f.jos_a;
+        const double t0 = -b[A] * f.inv_d[A];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b[a] = a == A ? 0.0 : fma(t0, f.d[a], b[a]);
+        scale = fabs(f.inv_d[A]);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        b[a] = f.o[a] + j * f.ej[a] + k * f.ek[a] + 0.5 * (n3[a] + 1.0);
-        ds[a] = (double)step * f.d[a];
+        ds[a] = (jos && a == f.jos_a) ? (f.d[a] > 0.0 ? 1.0 : -1.0) : scale * f.d[a];
         if (f.inv_d[a] != 0.0) {
             // index coordinate b + n ds must stay inside (0, n + 1)
-            double ia = f.inv_d[a] / (double)step;
+            double ia = (jos && a == f.jos_a) ? ds[a] : f.inv_d[a] / scale;
             double t1 = -b[a] * ia, t2 = (n3[a] + 1.0 - b[a]) * ia;
             tlo = fmax(tlo, fmin(t1, t2));
             thi = fmin(thi, fmax(t1, t2));
@@ -525,7 +539,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                                                int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
                                                float step, long long vol_pad, float *__restrict__ I,
                                                const int2 *__restrict__ sp, int kk, int C,
-                                               const float *__restrict__ cT, const int *__restrict__ gtab, int ng)
+                                               const float *__restrict__ cT, const int *__restrict__ gtab, int ng,
+                                               int jos)
 {
     constexpr int Q = UP / 4;      // float4 per staged voxel
     // FUSED: the map table int2[UP][kk] (global-memory gathers), the channel
@@ -555,7 +570,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
     }
     double b[3], ds[3];
     int n0 = 0, n1 = -1;
-    if (live) ray_setup(f, j, k, nx, ny, nz, step, b, ds, n0, n1);
+    if (live) ray_setup(f, j, k, nx, ny, nz, step, b, ds, n0, n1, jos != 0);
     float acc[UP];
 #pragma unroll
     for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
@@ -815,89 +830,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
         }
     }
     if (!live) return;
+    const float wgt = jos ? f.jos_w : step;  // Joseph: each cut weighs 1 / |d_A|
     float *out = I + (((long long)s * nj + j) * nk + k) * nseg;
 #pragma unroll
     for (int u = 0; u < UP; ++u) {
         if (u < U) {
-            for (int cseg = u; cseg < nseg; cseg += U) out[cseg] = step * acc[u];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Joseph's method forward (the paper's own projector, sect. 3.5): one thread
-// per ray; the ray is cut by every voxel-centre plane normal to its dominant
-// axis A, the field interpolated bilinearly from M in the two other axes at
-// each cut (zero border), and each cut weighted by 1/|d_A|.  Planes are in
-// padded index coordinates P = layer + 1; cuts whose in-plane coordinates
-// leave (0, n + 1) touch only the zero border and are skipped.
-// ---------------------------------------------------------------------------
-template <int UP>
-__global__ __launch_bounds__(256) void k_march_joseph(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
-                                                      int s0, int nx, int ny, int nz, int nj, int nk, int nseg,
-                                                      int U, long long vol_pad, float *__restrict__ I)
-{
-    const int ntj = (nj + kMarchTile - 1) / kMarchTile, ntk = (nk + kMarchTile - 1) / kMarchTile;
-    const int lb = blockIdx.x;
-    const int p = lb / (ntj * ntk), s = s0 + p;
-    const int tj = (lb / ntk) % ntj, tk = lb % ntk;
-    const int j = tj * kMarchTile + (threadIdx.x % kMarchTile);
-    const int k = tk * kMarchTile + (threadIdx.x / kMarchTile);
-    if (j >= nj || k >= nk) return;  // no block-level synchronisation below
-    const ProjFrame &f = frames[s];
-    const int A = f.jos_a, B = (A + 1) % 3, Cc = (A + 2) % 3;
-    const int n3[3] = {nx, ny, nz};
-    double b[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) b[a] = f.o[a] + j * f.ej[a] + k * f.ek[a] + 0.5 * (n3[a] + 1.0);
-    const double rB = f.d[B] * f.inv_d[A], rC = f.d[Cc] * f.inv_d[A];
-    // planes P in [1, n_A] whose cut lies inside (0, n + 1) along B and C
-    double plo = 1.0, phi = (double)n3[A];
-    const double rq[2] = {rB, rC};
-    const int qq[2] = {B, Cc};
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int q = qq[i];
-        if (rq[i] != 0.0) {
-            const double t1 = b[A] - b[q] / rq[i], t2 = b[A] + ((double)n3[q] + 1.0 - b[q]) / rq[i];
-            plo = fmax(plo, fmin(t1, t2));
-            phi = fmin(phi, fmax(t1, t2));
-        } else if (!(b[q] > 0.0 && b[q] < (double)n3[q] + 1.0)) {
-            phi = -1.0;
-        }
-    }
-    const long long str[3] = {(long long)(ny + 2) * (nz + 2) * UP, (long long)(nz + 2) * UP, (long long)UP};
-    const long long sA = str[A], sB = str[B], sC = str[Cc];
-    const float *Mp = M + (long long)p * vol_pad * UP;
-    float acc[UP];
-#pragma unroll
-    for (int u = 0; u < UP; ++u) acc[u] = 0.0f;
-    const int P0 = max(1, (int)ceil(plo)), P1 = min(n3[A], (int)floor(phi));
-    for (int P = P0; P <= P1; ++P) {
-        const double t = (double)P - b[A];
-        const double pB = fma(t, rB, b[B]), pC = fma(t, rC, b[Cc]);
-        const int iB = min(max((int)floor(pB), 0), n3[B]), iC = min(max((int)floor(pC), 0), n3[Cc]);
-        const float fB = (float)(pB - iB), fC = (float)(pC - iC);
-        const float w[4] = {(1.0f - fB) * (1.0f - fC), (1.0f - fB) * fC, fB * (1.0f - fC), fB * fC};
-        const float *q = Mp + P * sA + iB * sB + iC * sC;
-        const long long off[4] = {0, sC, sB, sB + sC};
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-#pragma unroll
-            for (int u4 = 0; u4 < UP; u4 += 4) {
-                const f4 m = *reinterpret_cast<const f4 *>(q + off[cc] + u4);
-                acc[u4 + 0] = fmaf(w[cc], m.x, acc[u4 + 0]);
-                acc[u4 + 1] = fmaf(w[cc], m.y, acc[u4 + 1]);
-                acc[u4 + 2] = fmaf(w[cc], m.z, acc[u4 + 2]);
-                acc[u4 + 3] = fmaf(w[cc], m.w, acc[u4 + 3]);
-            }
-        }
-    }
-    float *out = I + (((long long)s * nj + j) * nk + k) * nseg;
-#pragma unroll
-    for (int u = 0; u < UP; ++u) {
-        if (u < U) {
-            for (int cseg = u; cseg < nseg; cseg += U) out[cseg] = f.jos_w * acc[u];
+            for (int cseg = u; cseg < nseg; cseg += U) out[cseg] = wgt * acc[u];
         }
     }
 }
@@ -908,13 +846,9 @@ static hipError_t march_t(const Dims &d, const ProjFrame *frames, const float *M
 {
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * np);
-    if (d.joseph) {
-        hipLaunchKernelGGL(k_march_joseph<UP>, grid, dim3(kMarchTile * kMarchTile), 0, st, M, frames, s0, d.nx, d.ny,
-                           d.nz, d.nj, d.nk, d.nseg, d.U, vol_pad, I);
-        return hipGetLastError();
-    }
     hipLaunchKernelGGL((k_march<UP, false>), grid, dim3(kMarchTile * kMarchTile), d.march_lds, st, M, frames, s0,
-                       d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I, nullptr, 0, 0, nullptr, nullptr, 0);
+                       d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, vol_pad, I, nullptr, 0, 0, nullptr, nullptr, 0,
+                       d.joseph);
     return hipGetLastError();
 }
 
@@ -925,7 +859,7 @@ static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const fl
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * d.S);
     const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + (d.sparse_ng * (UP + 1) * 4 + 15) / 16 * 16 + d.march_lds;
     hipLaunchKernelGGL((k_march<UP, true>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx, d.ny,
-                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab, d.sparse_ng);
+                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab, d.sparse_ng, 0);
     return hipGetLastError();
 }
 
