@@ -93,3 +93,14 @@ def test_noalloc_is_independent_of_the_attached_workspace():
     P = gpu_projector(og, forward_batch=1)
     assert P.batch == 4  # one 16-row map tile: 4 projections x 4 unique segments
     _check(P, 13, weights=True, mu=0.5)
+
+
+@pytest.mark.parametrize("k", [1, 5])
+def test_noalloc_with_the_sparse_fused_forward(k):
+    """With a sparse map the scratch holds no mapped volumes, and for k = 1 the
+    channel-major copy of c (at most 8 kept channels per projection at 8
+    segments); the results equal the workspace entry point's bit for bit."""
+    torch.cuda.set_device(DEV)
+    P = gpu_projector(small(ell_max=4), sparse_k=k)
+    assert P.batch == 0
+    _check(P, 13 + k, weights=True, mu=1e-3)
