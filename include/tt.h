@@ -146,9 +146,9 @@ int tt_set_map_precision(tt_ctx *ctx, int precision);
  *     (between k = 0 and k >= 1, or across the channel-major threshold)
  *     releases the attached workspace: attach one sized by tt_workspace_bytes
  *     in the new mode before computing.
- * TT_EINVAL for k < 0; TT_EUNSUPPORTED for k >= 1 with Joseph's method or the
- * bf16 map tier (and tt_set_projector / tt_set_map_precision return
- * TT_EUNSUPPORTED for those while a sparse map is set). */
+ * Both projector models (tt_set_projector) run fused.  TT_EINVAL for k < 0;
+ * TT_EUNSUPPORTED for k >= 1 with the bf16 map tier (and tt_set_map_precision
+ * returns TT_EUNSUPPORTED for it while a sparse map is set). */
 int tt_set_sparse_map(tt_ctx *ctx, int k);
 
 /* Discretisation of the projection operator P_{sjk,xyz} (Eq. projection_operator):

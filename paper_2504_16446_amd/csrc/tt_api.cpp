@@ -440,8 +440,6 @@ int tt_set_projector(tt_ctx *c, int model)
     if (!c) return fail(TT_EINVAL, "null context");
     if (model != TT_PROJ_TRILINEAR && model != TT_PROJ_JOSEPH)
         return fail(TT_EINVAL, "model must be TT_PROJ_TRILINEAR or TT_PROJ_JOSEPH");
-    if (model == TT_PROJ_JOSEPH && c->d.sparse_k > 0)
-        return fail(TT_EUNSUPPORTED, "the sparse fused map supports the trilinear projector only");
     c->d.joseph = model == TT_PROJ_JOSEPH;
     // Joseph's cuts carry their own 1/|d_A| weight: no sample-spacing factor
     c->d.step = c->d.joseph ? 1.0f : (float)c->g.step;
@@ -463,7 +461,6 @@ int tt_set_sparse_map(tt_ctx *c, int k)
     if (!c) return fail(TT_EINVAL, "ctx is null");
     if (k < 0) return fail(TT_EINVAL, "k must be >= 0");
     const Dims &d = c->d;
-    if (k > 0 && d.joseph) return fail(TT_EUNSUPPORTED, "the sparse fused map supports the trilinear projector only");
     if (k > 0 && c->precision == TT_MAP_BF16) return fail(TT_EUNSUPPORTED, "the sparse fused map runs in float32 only");
     const int kk = std::min(k, d.C);
     std::vector<int2> sp;

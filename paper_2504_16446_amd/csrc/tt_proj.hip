@@ -859,7 +859,8 @@ static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const fl
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * d.S);
     const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + (d.sparse_ng * (UP + 1) * 4 + 15) / 16 * 16 + d.march_lds;
     hipLaunchKernelGGL((k_march<UP, true>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx, d.ny,
-                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab, d.sparse_ng, 0);
+                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab, d.sparse_ng,
+                       d.joseph);
     return hipGetLastError();
 }
 
@@ -887,7 +888,7 @@ __global__ __launch_bounds__(256) void k_channel_major(const float *__restrict__
 hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp,
                               const int *gtab, float *cT, float *I, hipStream_t st)
 {
-    if (d.sparse_k < 1 || d.joseph) return hipErrorInvalidValue;
+    if (d.sparse_k < 1) return hipErrorInvalidValue;
     const long long V = (long long)d.nx * d.ny * d.nz;
     if (d.sparse_cm)
         hipLaunchKernelGGL(k_channel_major, dim3((unsigned)std::min<long long>((V + 63) / 64, 4096)), dim3(256),

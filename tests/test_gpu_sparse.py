@@ -52,6 +52,11 @@ def _half_circle():
     return oracle.Geometry((9, 11, 10), 2, g.inner, g.outer, 12, 10, 6, synth.lab_frame(), seg_span=np.pi)
 
 
+def _joseph_small():
+    g = small(ell_max=8, n_seg=16)
+    return oracle.Geometry(g.n, g.ell_max, g.inner, g.outer, g.nj, g.nk, g.n_seg, synth.lab_frame(), model="joseph")
+
+
 def _nn():
     g = small(ell_max=0)
     return oracle.Geometry(g.n, 0, g.inner, g.outer, g.nj, g.nk, 8, synth.lab_frame(), basis="nn",
@@ -71,6 +76,9 @@ CASES = {
     "c1_k4": (lambda: workload("c1"), 4),
     "nn_k3_exact": (_nn, 3),                                   # nearest neighbour: n_sub nonzeros, kept exactly
     "nn_k1": (_nn, 1),
+    # Joseph's method: the cuts are samples of the same fused kernel
+    "joseph_small_k2": (_joseph_small, 2),
+    "joseph_steep_k3": (lambda: steep(model="joseph"), 3),
 }
 
 
@@ -172,16 +180,10 @@ def test_mode_switches_and_errors():
         call("tt_set_sparse_map", P._h, 2)
     assert e.value.code == -6
     call("tt_set_map_precision", P._h, 0)
-    call("tt_set_projector", P._h, 1)
-    with pytest.raises(TTError) as e:  # Joseph's method
-        call("tt_set_sparse_map", P._h, 2)
-    assert e.value.code == -6
-    call("tt_set_projector", P._h, 0)
     Ps = gpu_projector(og, sparse_k=2)
-    for fn in ("tt_set_projector", "tt_set_map_precision"):  # Joseph's method, bf16 tier
-        with pytest.raises(TTError) as e:
-            call(fn, Ps._h, 1)
-        assert e.value.code == -6
+    with pytest.raises(TTError) as e:  # bf16 tier
+        call("tt_set_map_precision", Ps._h, 1)
+    assert e.value.code == -6
     # a workspace below the fused size (channel-major copy included) is refused
     small_bytes = int(call("tt_workspace_bytes", Ps._h, 0)) - 4096
     buf = torch.empty(small_bytes, dtype=torch.uint8, device=DEV)
