@@ -382,6 +382,38 @@ def sparse_bench(w, dev, ks=(1, 2, 0), reps=2):
     return out
 
 
+def measured_hbm(dev, gib=4, reps=5):
+    """What the HBM sustains for plain streams (torch's own kernels): a device
+    copy (read + write bytes), a fill (writes) and a sum (reads) over gib GiB,
+    averaged over reps launches timed with events on the current stream."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    nbytes = 4 * n
+    out = {"bytes": nbytes,
+           "copy_GBps": 2 * nbytes / timed(lambda: b.copy_(a)) / 1e9,
+           "fill_GBps": nbytes / timed(lambda: b.fill_(0.5)) / 1e9,
+           "read_GBps": nbytes / timed(lambda: torch.sum(a)) / 1e9,
+           "kernels": "torch copy_, fill_ and sum over float32 buffers"}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -540,6 +572,8 @@ def main():
     regs = None if args.no_extras else regulariser_bench(dev)
     print("[bench] sparse fused forward ...", file=sys.stderr, flush=True)
     sparse = None if args.no_extras else sparse_bench(w, dev)
+    print("[bench] measured HBM streams ...", file=sys.stderr, flush=True)
+    hbm = None if args.no_extras else measured_hbm(dev)
     print("[bench] warm-start network layers ...", file=sys.stderr, flush=True)
     if args.no_extras:
         netb = None
@@ -573,6 +607,7 @@ def main():
         "regularisers": regs,
         "sparse_fused": sparse,
         "network": netb,
+        "measured_hbm": hbm,
     }
     print(json.dumps(line), flush=True)
 
