@@ -54,6 +54,7 @@ CASES = {
     "axis_ties": _axis_ties,
     "small_l4": lambda: _jos(small(ell_max=4)),
     "small_l8_seg16": lambda: _jos(small(ell_max=8, n_seg=16)),
+    "small_l8_seg32": lambda: _jos(small(ell_max=8, n_seg=32)),   # sixteen unique segments
     "half_circle": lambda: oracle.Geometry((9, 11, 10), 2, *tilted_angles(3, (0.0, 33.0)), 12, 10, 6,
                                            synth.lab_frame(), seg_span=np.pi, model="joseph"),
     "steep_tilts": lambda: steep(model="joseph"),

@@ -62,6 +62,13 @@ CASES = {
     # LDS (detector offsets, a non-unit step, steep tilts)
     "tiny_offsets_step_seg16": lambda: tiny(offsets=True, step=0.8, n_seg=16),
     "steep_seg16": lambda: steep(n_seg=16),
+    # sixteen unique segments (the widest layout: four float4 per mapped voxel)
+    "small_l4_seg32": lambda: small(ell_max=4, n_seg=32),
+    "small_l8_seg32": lambda: small(ell_max=8, n_seg=32),
+    "steep_seg32": lambda: steep(n_seg=32),
+    # twelve distinct segments over a half circle: padded to sixteen channels
+    "half_circle_seg12": lambda: oracle.Geometry((9, 11, 10), 2, tiny().inner, tiny().outer, 12, 10, 12,
+                                                 synth.lab_frame(), seg_span=np.pi),
 }
 
 
@@ -94,7 +101,7 @@ def test_adjoint_parity(name):
     assert rel_max(got, ref) <= 10 * TOL
 
 
-@pytest.mark.parametrize("name", ["tiny_offsets_step", "small_l8_seg16", "c1"])
+@pytest.mark.parametrize("name", ["tiny_offsets_step", "small_l8_seg16", "c1", "small_l8_seg32"])
 def test_loss_grad_parity(name):
     og = _geom(name)
     c, data = _inputs(og, 3)

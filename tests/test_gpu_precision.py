@@ -35,10 +35,10 @@ def _t(a):
 def _geom(name):
     return {"small_l4": lambda: small(ell_max=4), "small_l8_seg16": lambda: small(ell_max=8, n_seg=16),
             "small_l6": lambda: small(ell_max=6), "c1": lambda: workload("c1"),
-            "small_l10": lambda: small(ell_max=10)}[name]()
+            "small_l10": lambda: small(ell_max=10), "small_l8_seg32": lambda: small(ell_max=8, n_seg=32)}[name]()
 
 
-@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1", "small_l10"])
+@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1", "small_l10", "small_l8_seg32"])
 def test_bf16_forward(name):
     og = _geom(name)
     rng = np.random.default_rng(41)
@@ -58,7 +58,7 @@ def test_bf16_forward(name):
     assert rel_l2(P.forward(_t(c)).cpu().numpy(), ref) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1", "small_l10"])
+@pytest.mark.parametrize("name", ["small_l4", "small_l8_seg16", "small_l6", "c1", "small_l10", "small_l8_seg32"])
 def test_bf16_adjoint(name):
     og = _geom(name)
     rng = np.random.default_rng(42)

@@ -70,6 +70,7 @@ CASES = {
     "small_l8_seg16_k4": (lambda: small(ell_max=8, n_seg=16), 4),
     "small_l8_dense": (lambda: small(ell_max=8), 45),        # k = C: the exact map, fused
     "small_l12_seg16_k6": (lambda: small(ell_max=12, n_seg=16), 6),
+    "small_l8_seg32_k3": (lambda: small(ell_max=8, n_seg=32), 3),   # sixteen unique segments
     "half_circle_k2": (_half_circle, 2),                       # no antipodal fold: 6 distinct segments
     "steep_k3": (lambda: steep(), 3),                          # global-memory gather inside the fused kernel
     "degenerate_k2": (lambda: degenerate(), 2),
