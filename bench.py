@@ -383,9 +383,11 @@ def sparse_bench(w, dev, ks=(1, 2, 0), reps=2):
 
 
 def measured_hbm(dev, gib=4, reps=5):
-    """What the HBM sustains for plain streams (torch's own kernels): a device
-    copy (read + write bytes), a fill (writes) and a sum (reads) over gib GiB,
-    averaged over reps launches timed with events on the current stream."""
+    """What the HBM sustains for plain streams under torch's own kernels (lower
+    bounds of the hardware's rates): a device copy (read + write bytes), a fill
+    (writes) and a dot product of two buffers (reads; the best of torch's
+    reductions, sum and max read ~10% slower) over gib GiB each, averaged over
+    reps launches timed with events on the current stream."""
     import torch
     n = gib * (1 << 30) // 4
     a = torch.ones(n, device=dev)
@@ -407,8 +409,8 @@ def measured_hbm(dev, gib=4, reps=5):
     out = {"bytes": nbytes,
            "copy_GBps": 2 * nbytes / timed(lambda: b.copy_(a)) / 1e9,
            "fill_GBps": nbytes / timed(lambda: b.fill_(0.5)) / 1e9,
-           "read_GBps": nbytes / timed(lambda: torch.sum(a)) / 1e9,
-           "kernels": "torch copy_, fill_ and sum over float32 buffers"}
+           "read_GBps": 2 * nbytes / timed(lambda: torch.dot(a, b)) / 1e9,
+           "kernels": "torch copy_, fill_ and dot over float32 buffers"}
     del a, b
     torch.cuda.empty_cache()
     return out

@@ -62,6 +62,9 @@ CASES = {
     # LDS (detector offsets, a non-unit step, steep tilts)
     "tiny_offsets_step_seg16": lambda: tiny(offsets=True, step=0.8, n_seg=16),
     "steep_seg16": lambda: steep(n_seg=16),
+    # sample steps above one voxel (fewer samples than planes along the ray)
+    "tiny_step_1p5_seg16": lambda: tiny(offsets=True, step=1.5, n_seg=16),
+    "tiny_step_2": lambda: tiny(step=2.0),
     # sixteen unique segments (the widest layout: four float4 per mapped voxel)
     "small_l4_seg32": lambda: small(ell_max=4, n_seg=32),
     "small_l8_seg32": lambda: small(ell_max=8, n_seg=32),
