@@ -211,9 +211,10 @@ def warm_vs_plain_heldout(dev, n=4, plain_iters=30):
             "note": "warm time includes the scale kappa, backprojection, inference and blending"}
 
 
-def precision_report(dev, n_rays=128, n_vox=16):
+def precision_report(dev, n_rays=128, n_vox=16, reps=3):
     """Errors of the fp32 and bf16 map tiers against the float64 oracle on the
-    128^3 / ell_max 8 / 300-projection / 16-segment workload (sampled outputs)."""
+    128^3 / ell_max 8 / 300-projection / 16-segment workload (sampled outputs),
+    and each tier's kernel times per forward + adjoint."""
     import numpy as np
     import torch
     import oracle
@@ -243,6 +244,16 @@ def precision_report(dev, n_rays=128, n_vox=16):
         got_a = g[xyz[:, 0], xyz[:, 1], xyz[:, 2]].cpu().numpy().astype(np.float64)
         out[tier] = {"forward_rel_l2": float(np.linalg.norm(got_f - ref_f) / np.linalg.norm(ref_f)),
                      "adjoint_rel_l2": float(np.linalg.norm(got_a - ref_a) / np.linalg.norm(ref_a))}
+        # per-kernel times of the tier (event-timed, 3 forward + adjoint passes)
+        torch.cuda.synchronize()
+        P.timing(True)
+        P.timing_read()
+        for _ in range(reps):
+            P.forward(ct, out=I)
+            P.adjoint(yt, out=g)
+        kt = P.timing_read()
+        P.timing(False)
+        out[tier]["kernels_ms"] = {k: ms / reps for k, (ms, n) in kt.items() if n}
     return out
 
 

@@ -374,10 +374,151 @@ __global__ __launch_bounds__(256) void k_map_bf16(const float *__restrict__ c, c
     }
 }
 
+// Register-resident bf16 variant for Cp <= 64, organised as k_map_fp32_rb: a
+// block of kMapWaves waves covers 256 rows, each wave 16 / NW row tiles with
+// its A operands for every k-step in registers; the block walks a contiguous
+// range of 64-voxel tiles (sequential M store streams), prefetching the next
+// tile's coefficients into registers during the MFMAs, and rounds them to
+// bf16 while staging them in LDS.  Same rounding points and MFMA order as
+// k_map_bf16, hence the same results.
+template <int UP, int CPT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_map_bf16_rb(const float *__restrict__ c, const short *__restrict__ Bsw16,
+                                                         int V, int C, int ny, int nz, int s0, int np,
+                                                         long long vol_pad, float *__restrict__ M)
+{
+    constexpr int Cp = 16 * CPT, KP = CPT / 2, ODD = CPT & 1;
+    constexpr int ld = Cp + 8;                  // LDS row of one voxel, in shorts (16-byte multiple)
+    constexpr int NT = 64 * NW;                 // threads of the block
+    constexpr int MW = 16 / NW;                 // row tiles per wave (256 rows per block)
+    constexpr int NPF = (16 * Cp + NT - 1) / NT;  // float4 per thread covering a 64 x C tile (C <= Cp)
+    __shared__ short cb[64 * ld];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kq = lane >> 4;
+    const int rt0 = (s0 * UP) / 16 + blockIdx.y * 16 + wave * MW;
+    s8 a8[MW][KP > 0 ? KP : 1];
+    s4 a4[MW];
+#pragma unroll
+    for (int mt = 0; mt < MW; ++mt) {
+        const short *rt = Bsw16 + (long long)(rt0 + mt) * 16 * Cp;
+#pragma unroll
+        for (int kp = 0; kp < KP; ++kp) a8[mt][kp] = *reinterpret_cast<const s8 *>(rt + (kp * 64 + lane) * 8);
+        if constexpr (ODD) a4[mt] = *reinterpret_cast<const s4 *>(rt + KP * 512 + lane * 4);
+    }
+    // coefficients C..ld-1 of every voxel row stay zero for every tile
+    for (int e = tid; e < 64 * (ld - C); e += NT) cb[(e / (ld - C)) * ld + C + e % (ld - C)] = 0;
+    const int ntiles = (V + 63) / 64;
+    const int n4 = 16 * C;  // float4 in a full tile
+    const float invC = 1.0f / (float)C;
+    f4 pf[NPF];
+    auto prefetch = [&](int t) {
+        const int nvals = min(64, V - t * 64) * C;
+        const f4 *src = reinterpret_cast<const f4 *>(c + (long long)t * 64 * C);  // 256 C bytes per tile: aligned
+        const float *srcf = c + (long long)t * 64 * C;
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int e4 = tid + NT * i;
+            pf[i] = f4{0.f, 0.f, 0.f, 0.f};
+            if (4 * e4 + 3 < nvals) {
+                pf[i] = src[e4];
+            } else if (4 * e4 < nvals) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * e4 + q < nvals) pf[i][q] = srcf[4 * e4 + q];
+            }
+        }
+    };
+    const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int tend = min(ntiles, (int)blockIdx.x * per + per);
+    int tile = blockIdx.x * per;
+    if (tile < tend) prefetch(tile);
+    for (; tile < tend; ++tile) {
+        __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            const int e4 = tid + NT * i;
+            if (e4 < n4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * e4 + q;
+                    const int v = (int)(((float)e + 0.5f) * invC);
+                    cb[v * ld + (e - v * C)] = f2bf(pf[i][q]);
+                }
+            }
+        }
+        __syncthreads();
+        if (tile + 1 < tend) prefetch(tile + 1);  // in flight during the MFMAs
+        f4 acc[4][MW];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MW; ++mt) acc[nt][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kp = 0; kp < KP; ++kp) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const s8 b = *reinterpret_cast<const s8 *>(cb + (nt * 16 + (lane & 15)) * ld + kp * 32 + 8 * kq);
+#pragma unroll
+                for (int mt = 0; mt < MW; ++mt) acc[nt][mt] = mfma16x16x32bf16(a8[mt][kp], b, acc[nt][mt]);
+            }
+        }
+        if constexpr (ODD) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const s4 b = *reinterpret_cast<const s4 *>(cb + (nt * 16 + (lane & 15)) * ld + KP * 32 + 4 * kq);
+#pragma unroll
+                for (int mt = 0; mt < MW; ++mt) acc[nt][mt] = mfma16x16x16bf16(a4[mt], b, acc[nt][mt]);
+            }
+        }
+        const int v0 = tile * 64;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int v = v0 + nt * 16 + (lane & 15);
+            if (v >= V) continue;
+            const long long vp = pad_index(v, ny, nz);
+#pragma unroll
+            for (int mt = 0; mt < MW; ++mt) {
+                const int row = blockIdx.y * 256 + wave * 16 * MW + mt * 16 + 4 * kq;  // within the batch
+                const int p = row / UP, u0 = row % UP;
+                if (p < np) *reinterpret_cast<f4 *>(M + (long long)p * vol_pad * UP + vp * UP + u0) = acc[nt][mt];
+            }
+        }
+    }
+}
+
+template <int UP, int CPT>
+static hipError_t map_bf16_rb_t(const Dims &d, const float *c, const uint16_t *Bsw16, int s0, int np, float *M,
+                                hipStream_t st)
+{
+    const int V = d.nx * d.ny * d.nz;
+    const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
+    const int gy = (np * UP + 255) / 256, ntiles = (V + 63) / 64;
+    static const int resident = [] {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_map_bf16_rb<UP, CPT, kMapWaves>, 64 * kMapWaves,
+                                                         0) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 512;
+        return std::max(1, per_cu * cus);
+    }();
+    const int gx = std::max(1, std::min(ntiles, resident / gy));
+    hipLaunchKernelGGL((k_map_bf16_rb<UP, CPT, kMapWaves>), dim3(gx, gy), dim3(64 * kMapWaves), 0, st, c,
+                       reinterpret_cast<const short *>(Bsw16), V, d.C, d.ny, d.nz, s0, np, vol_pad, M);
+    return hipGetLastError();
+}
+
 template <int UP>
 static hipError_t map_bf16_t(const Dims &d, const float *c, const uint16_t *Bsw16, int s0, int np, float *M,
                              hipStream_t st)
 {
+    const bool aligned = reinterpret_cast<uintptr_t>(c) % 16 == 0;  // float4 tile loads
+    switch (aligned ? d.Cp : 0) {
+    case 16: return map_bf16_rb_t<UP, 1>(d, c, Bsw16, s0, np, M, st);
+    case 32: return map_bf16_rb_t<UP, 2>(d, c, Bsw16, s0, np, M, st);
+    case 48: return map_bf16_rb_t<UP, 3>(d, c, Bsw16, s0, np, M, st);
+    case 64: return map_bf16_rb_t<UP, 4>(d, c, Bsw16, s0, np, M, st);
+    default: break;  // larger orders: one tile per block, A operands loaded per step
+    }
     const int V = d.nx * d.ny * d.nz;
     const long long vol_pad = (long long)(d.nx + 2) * (d.ny + 2) * (d.nz + 2);
     dim3 grid((V + 63) / 64, (np * UP + 255) / 256);
