@@ -101,9 +101,9 @@ struct Dims {
 
 // The fused forward stages from a channel-major copy of c when no projection
 // keeps more than this many basis functions over its unique segments, and
-// from the coefficient records c[v][0..C) otherwise (measured: with 8 or
-// fewer channels the per-channel arrays cost less than whole 4C-byte records).
-constexpr int kFusedCmChannels = 8;
+// from the coefficient records c[v][0..C) otherwise (the per-channel arrays,
+// whose loads run together, cost less than whole 4C-byte records).
+constexpr int kFusedCmChannels = 16;
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
 hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,

@@ -682,7 +682,7 @@ __device__ __forceinline__ void march_global_fused(const float *__restrict__ cv,
 // segment values are formed while staging, m_u = sum_t tab[u][t].w *
 // c[v][tab[u][t].i] over the kk kept basis functions of (s, u); one thread
 // stages one (voxel, segment) pair.  The gather from the box is the same.
-template <int UP, bool FUSED>
+template <int UP, bool FUSED, int NCM = 8>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 && !FUSED) ? 5 : 1))) void k_march(const float *__restrict__ M, const ProjFrame *__restrict__ frames,
                                                int s0, int nx, int ny, int nz, int nj, int nk, int nseg, int U,
                                                float step, long long vol_pad, float *__restrict__ I,
@@ -832,17 +832,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                 for (int e0 = threadIdx.x; e0 < nbox; e0 += 512) {
                     long long v0, v1;
                     const bool in0 = voxel(e0, v0), in1 = voxel(e0 + 256, v1);
+                    // all (ng <= NCM) channel loads of both voxels in flight
+                    // together, then the weighted sums
+                    float x0[NCM], x1[NCM];
+#pragma unroll
+                    for (int g = 0; g < NCM; ++g) {
+                        x0[g] = x1[g] = 0.0f;
+                        if (g < ng) {
+                            const float *ch = cT + (long long)gch[g] * V;
+                            x0[g] = ch[v0];
+                            x1[g] = ch[v1];
+                        }
+                    }
                     float m0[UP], m1[UP];
 #pragma unroll
                     for (int u = 0; u < UP; ++u) m0[u] = m1[u] = 0.0f;
-                    for (int g = 0; g < ng; ++g) {
-                        const float *ch = cT + (long long)gch[g] * V;
-                        const float x0 = ch[v0], x1 = ch[v1];
 #pragma unroll
-                        for (int u = 0; u < UP; ++u) {
-                            const float wv = gw[g * UP + u];
-                            m0[u] = fmaf(wv, x0, m0[u]);
-                            m1[u] = fmaf(wv, x1, m1[u]);
+                    for (int g = 0; g < NCM; ++g) {
+                        if (g < ng) {
+#pragma unroll
+                            for (int u = 0; u < UP; ++u) {
+                                const float wv = gw[g * UP + u];
+                                m0[u] = fmaf(wv, x0[g], m0[u]);
+                                m1[u] = fmaf(wv, x1[g], m1[u]);
+                            }
                         }
                     }
 #pragma unroll
@@ -1006,9 +1019,17 @@ static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const fl
 {
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * d.S);
     const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + (d.sparse_ng * (UP + 1) * 4 + 15) / 16 * 16 + d.march_lds;
-    hipLaunchKernelGGL((k_march<UP, true>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx, d.ny,
-                       d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab, d.sparse_ng,
-                       d.joseph);
+    // channel-major staging unrolled for up to 8 or up to kFusedCmChannels
+    // channels (the wider form costs registers that narrow lists do not need)
+    if (cT && d.sparse_ng > kFusedCmChannels) return hipErrorInvalidValue;
+    if (cT && d.sparse_ng > 8)
+        hipLaunchKernelGGL((k_march<UP, true, kFusedCmChannels>), grid, dim3(kMarchTile * kMarchTile), lds, st, c,
+                           frames, 0, d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C,
+                           cT, gtab, d.sparse_ng, d.joseph);
+    else
+        hipLaunchKernelGGL((k_march<UP, true, 8>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab,
+                           d.sparse_ng, d.joseph);
     return hipGetLastError();
 }
 
