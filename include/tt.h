@@ -135,7 +135,7 @@ int tt_set_map_precision(tt_ctx *ctx, int precision);
  *     runs one fused kernel for all projections that forms the unique segment
  *     values sum_t B_{sc,i_t} c_{v,i_t} of each voxel while staging the
  *     coefficient volume for the ray sums (no mapped volumes in the
- *     workspace).  When no projection keeps more than 16 basis functions over
+ *     workspace).  When no projection keeps more than 32 basis functions over
  *     its unique segments, tt_project first copies c channel-major into the
  *     workspace (C x nx ny nz floats) and the staging reads only the kept
  *     channels; otherwise it reads the coefficient records.  tt_adjoint,
@@ -184,7 +184,7 @@ int tt_sizes(const tt_ctx *ctx, int64_t *out8);
  * (rounded to what the map kernel accepts; forward_batch = 1 gives the
  * smallest valid workspace, >= n_proj the whole set in one batch;
  * forward_batch <= 0 gives the workspace without mapped volumes, which serves
- * only the fused forward of tt_set_sparse_map; with a sparse map of at most 16
+ * only the fused forward of tt_set_sparse_map; with a sparse map of at most 32
  * kept basis functions per projection the workspace also holds a
  * channel-major copy of c, nx ny nz C floats).
  * tt_set_workspace attaches caller memory (device, 256-byte aligned) and

@@ -103,7 +103,7 @@ struct Dims {
 // keeps more than this many basis functions over its unique segments, and
 // from the coefficient records c[v][0..C) otherwise (the per-channel arrays,
 // whose loads run together, cost less than whole 4C-byte records).
-constexpr int kFusedCmChannels = 16;
+constexpr int kFusedCmChannels = 32;
 
 // M[p][(nx+2)(ny+2)(nz+2)][Up] = Bu[s0+p] c for p < np (zero border untouched).
 hipError_t launch_map_fp32(const Dims &d, const float *c, const float *Bu, int s0, int np, float *M,

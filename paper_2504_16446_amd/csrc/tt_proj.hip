@@ -1019,13 +1019,18 @@ static hipError_t march_fused_t(const Dims &d, const ProjFrame *frames, const fl
 {
     dim3 grid(((d.nk + kMarchTile - 1) / kMarchTile) * ((d.nj + kMarchTile - 1) / kMarchTile) * d.S);
     const int lds = (UP * d.sparse_k * 8 + 15) / 16 * 16 + (d.sparse_ng * (UP + 1) * 4 + 15) / 16 * 16 + d.march_lds;
-    // channel-major staging unrolled for up to 8 or up to kFusedCmChannels
-    // channels (the wider form costs registers that narrow lists do not need)
+    // channel-major staging unrolled for up to 8, 16 or kFusedCmChannels
+    // channels (the wider forms cost registers that narrow lists do not need)
+    static_assert(kFusedCmChannels == 32, "the widths below");
     if (cT && d.sparse_ng > kFusedCmChannels) return hipErrorInvalidValue;
-    if (cT && d.sparse_ng > 8)
-        hipLaunchKernelGGL((k_march<UP, true, kFusedCmChannels>), grid, dim3(kMarchTile * kMarchTile), lds, st, c,
-                           frames, 0, d.nx, d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C,
-                           cT, gtab, d.sparse_ng, d.joseph);
+    if (cT && d.sparse_ng > 16)
+        hipLaunchKernelGGL((k_march<UP, true, 32>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab,
+                           d.sparse_ng, d.joseph);
+    else if (cT && d.sparse_ng > 8)
+        hipLaunchKernelGGL((k_march<UP, true, 16>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx,
+                           d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab,
+                           d.sparse_ng, d.joseph);
     else
         hipLaunchKernelGGL((k_march<UP, true, 8>), grid, dim3(kMarchTile * kMarchTile), lds, st, c, frames, 0, d.nx,
                            d.ny, d.nz, d.nj, d.nk, d.nseg, d.U, d.step, 0LL, I, sp, d.sparse_k, d.C, cT, gtab,

@@ -98,10 +98,10 @@ def test_noalloc_is_independent_of_the_attached_workspace():
 @pytest.mark.parametrize("k", [1, 6])
 def test_noalloc_with_the_sparse_fused_forward(k):
     """With a sparse map the scratch holds no mapped volumes, and for k = 1 the
-    channel-major copy of c (at most 16 kept channels per projection; k = 6
-    keeps 17-21 of the 45 and stages from the coefficient records); the
+    channel-major copy of c (at most 32 kept channels per projection; k = 6
+    keeps 29-41 of the 91 and stages from the coefficient records); the
     results equal the workspace entry point's bit for bit."""
     torch.cuda.set_device(DEV)
-    P = gpu_projector(small(ell_max=8), sparse_k=k)
+    P = gpu_projector(small(ell_max=12, n_seg=16), sparse_k=k)
     assert P.batch == 0
     _check(P, 13 + k, weights=True, mu=1e-3)
