@@ -829,43 +829,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                     }
                     return in;
                 };
-                for (int e0 = threadIdx.x; e0 < nbox; e0 += 512) {
-                    long long v0, v1;
-                    const bool in0 = voxel(e0, v0), in1 = voxel(e0 + 256, v1);
-                    // all (ng <= NCM) channel loads of both voxels in flight
-                    // together, then the weighted sums
-                    float x0[NCM], x1[NCM];
+                // EPI voxels per thread and pass (e = t, t + 256, ...), all
+                // their (ng <= NCM) channel loads in flight together, then the
+                // weighted sums
+                constexpr int EPI = NCM <= 8 ? 4 : 2;
+                for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * EPI) {
+                    long long vv[EPI];
+                    bool in[EPI];
+#pragma unroll
+                    for (int i = 0; i < EPI; ++i) in[i] = voxel(e0 + 256 * i, vv[i]);
+                    float x[EPI][NCM];
 #pragma unroll
                     for (int g = 0; g < NCM; ++g) {
-                        x0[g] = x1[g] = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < EPI; ++i) x[i][g] = 0.0f;
                         if (g < ng) {
                             const float *ch = cT + (long long)gch[g] * V;
-                            x0[g] = ch[v0];
-                            x1[g] = ch[v1];
+#pragma unroll
+                            for (int i = 0; i < EPI; ++i) x[i][g] = ch[vv[i]];
                         }
                     }
-                    float m0[UP], m1[UP];
+                    float m[EPI][UP];
 #pragma unroll
-                    for (int u = 0; u < UP; ++u) m0[u] = m1[u] = 0.0f;
+                    for (int i = 0; i < EPI; ++i)
+#pragma unroll
+                        for (int u = 0; u < UP; ++u) m[i][u] = 0.0f;
 #pragma unroll
                     for (int g = 0; g < NCM; ++g) {
                         if (g < ng) {
 #pragma unroll
                             for (int u = 0; u < UP; ++u) {
                                 const float wv = gw[g * UP + u];
-                                m0[u] = fmaf(wv, x0[g], m0[u]);
-                                m1[u] = fmaf(wv, x1[g], m1[u]);
+#pragma unroll
+                                for (int i = 0; i < EPI; ++i) m[i][u] = fmaf(wv, x[i][g], m[i][u]);
                             }
                         }
                     }
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        box[q * nbs + e0] = in0 ? f4{m0[4 * q], m0[4 * q + 1], m0[4 * q + 2], m0[4 * q + 3]}
-                                                : f4{0.f, 0.f, 0.f, 0.f};
-                        if (e0 + 256 < nbox)
-                            box[q * nbs + e0 + 256] = in1 ? f4{m1[4 * q], m1[4 * q + 1], m1[4 * q + 2], m1[4 * q + 3]}
-                                                          : f4{0.f, 0.f, 0.f, 0.f};
-                    }
+                    for (int q = 0; q < Q; ++q)
+#pragma unroll
+                        for (int i = 0; i < EPI; ++i)
+                            if (e0 + 256 * i < nbox)
+                                box[q * nbs + e0 + 256 * i] =
+                                    in[i] ? f4{m[i][4 * q], m[i][4 * q + 1], m[i][4 * q + 2], m[i][4 * q + 3]}
+                                          : f4{0.f, 0.f, 0.f, 0.f};
                 }
               } else {
                 // work item (box voxel e, segment u = thread mod UP), VS voxels per
