@@ -832,7 +832,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
                 // EPI voxels per thread and pass (e = t, t + 256, ...), all
                 // their (ng <= NCM) channel loads in flight together, then the
                 // weighted sums
-                constexpr int EPI = NCM <= 8 ? 4 : 2;
+                constexpr int EPI = NCM <= 16 ? 4 : 2;
                 for (int e0 = threadIdx.x; e0 < nbox; e0 += 256 * EPI) {
                     long long vv[EPI];
                     bool in[EPI];
