@@ -116,10 +116,11 @@ hipError_t launch_march(const Dims &d, const ProjFrame *frames, const float *M, 
 // Fused sparse forward: I[s][j][k][c] = step * ray sums over projection s of
 // m_u(v) = sum_t w_t c[v][i_t] with (i_t, w_t) = sp[s][u][t] (int2: basis index,
 // float bits), t < d.sparse_k, u = c mod U; all projections in one launch.
-// The staged voxels read the channel-major copy cT[i][v] (written first, V C
-// floats of caller workspace) through the per-projection channel list gtab[s] =
-// {ng channel indices, then ng x Up constants as float bits}; rays that gather
-// from global memory use sp and c.
+// With d.sparse_cm the staged voxels read the channel-major copy cT[i][v]
+// (written first, V C floats of caller workspace) through the per-projection
+// channel list gtab[s] = {ng channel indices, then ng x Up constants as float
+// bits}; otherwise they read the coefficient records c[v][i] through sp.  Rays
+// that gather from global memory use sp and c.
 hipError_t launch_march_fused(const Dims &d, const ProjFrame *frames, const float *c, const int2 *sp,
                               const int *gtab, float *cT, float *I, hipStream_t st);
 // yf[s][j][k][u] = scale * sum_{c: c mod U = u} y[s][j][k][c] (optionally

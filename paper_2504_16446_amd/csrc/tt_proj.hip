@@ -803,10 +803,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((UP == 4 &&
             if constexpr (FUSED) {
               if (cT) {
                 // thread t stages box elements e = t + 256 i (the walk of the
-                // copying path), two at a time: the ng selected channels of each
-                // voxel come from the channel-major copy cT[i][voxel], so a wave's
-                // loads of one channel are 64 consecutive z voxels; the unique
-                // segment values m_u = sum_g w[g][u] cT[g] are written as Q float4s
+                // copying path), EPI of them per pass: the ng selected channels of
+                // each voxel come from the channel-major copy cT[i][voxel], so a
+                // wave's loads of one channel are 64 consecutive z voxels; the
+                // unique segment values m_u = sum_g w[g][u] cT[g] are written as
+                // Q float4s
                 const long long V = (long long)nx * ny * nz;
                 const int nA = A == 0 ? nx : ny, nB = A == 0 ? ny : nx;
                 int pl = e_pl, ib = e_ib, iz = e_iz;
