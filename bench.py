@@ -358,7 +358,7 @@ def joseph_bench(w, dev, reps=3):
             "algorithmic_GBps": bytes_ / (total * 1e-3) / 1e9}
 
 
-def sparse_bench(w, dev, ks=(1, 2, 0), reps=2):
+def sparse_bench(w, dev, ks=(1, 2, 4, 0), reps=2):
     """Sparse fused forward (sect. "Pipelines"): the forward with the k
     largest basis constants per projection and segment in one fused kernel
     (no mapped volumes), against the two-pass map + march with the exact
