@@ -364,7 +364,8 @@ int tt_create(const tt_geometry *geom, tt_ctx **out)
     // 20-76 KiB on 100^3 x 4 and of 32-76 KiB on 128^3 and 256^3 x 8
     d.march_lds = plan_slabs(c->frames, d.Up, (d.Up == 4 ? 52 : 76) * 1024);
     d.win_ok = backproject_window_fits(c->frames) ? 1 : 0;
-    d.pw_lds = backproject_pw_lds(c->frames, d.Up, d.pw_wr, d.pw_wc);
+    d.pw_lds = backproject_pw_lds(c->frames, d.Up, false, d.pw_wr, d.pw_wc);
+    d.pwj_lds = backproject_pw_lds(c->frames, d.Up, true, d.pwj_wr, d.pwj_wc);
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

@@ -217,6 +217,7 @@ void build_frames(const Geometry &g, std::vector<ProjFrame> &frames, std::vector
             f.jos_igk[0] = std::fabs(gkB) > 1e-6 ? (float)(1.0 / gkB) : kFlatInv;
             f.jos_igk[1] = std::fabs(gkC) > 1e-6 ? (float)(1.0 / gkC) : kFlatInv;
             f.jos_rj = (float)((std::fabs(gkB) + std::fabs(gkC)) / std::fabs(det));
+            f.jos_rk = (float)((std::fabs(gjB) + std::fabs(gjC)) / std::fabs(det));
         }
         for (int a = 0; a < 3; ++a) {
             f.ejf[a] = (float)f.ej[a];

@@ -58,12 +58,12 @@ struct ProjFrame {
     // a ray's cut from a voxel centre in the voxel's layer is
     // Delta_{B,C} = dj * jos_gj + dk * jos_gk (B = (A+1)%3, C = (A+2)%3) for
     // detector offsets (dj, dk) from the voxel's own position, and the
-    // support |Delta_B|, |Delta_C| < 1 needs |dj| < jos_rj.
+    // support |Delta_B|, |Delta_C| < 1 needs |dj| < jos_rj and |dk| < jos_rk.
     int jos_a;
     float jos_w;
     float jos_gj[2], jos_gk[2];
     float jos_igk[2];  // 1 / jos_gk, or kFlatInv where |jos_gk| <= 1e-6 (see inv_df)
-    float jos_rj;
+    float jos_rj, jos_rk;
 };
 
 constexpr int kMarchTile = 16;  // rays per tile edge in the forward march
@@ -93,6 +93,7 @@ struct Dims {
                         //    adjoint's LDS window (trilinear model, eight unique segments)
     int pw_lds, pw_wr, pw_wc;  // paired + windowed adjoint: dynamic LDS bytes (0: not used) and
                                // window rows / columns
+    int pwj_lds, pwj_wr, pwj_wc;  // the same for Joseph's method
     int sparse_k = 0;   // 0: exact basis constants, map + march; >= 1: kept basis functions per
                         //    (projection, segment) of the sparse map, fused forward
     int sparse_ng = 0;  // fused forward: channels per projection's list (the most any projection uses)
@@ -141,7 +142,7 @@ hipError_t launch_backproject(const Dims &d, const ProjFrame *frames, const floa
 int backproject_blocks(const Dims &d);
 int backproject_blocks_max(const Dims &d);
 bool backproject_window_fits(const std::vector<ProjFrame> &frames);
-int backproject_pw_lds(const std::vector<ProjFrame> &frames, int up, int &wr, int &wc);
+int backproject_pw_lds(const std::vector<ProjFrame> &frames, int up, bool jos, int &wr, int &wc);
 
 // Derived per-voxel quantities: out[v][kPropFields] from c[v][C] (tt_props.hip).
 constexpr int kPropFields = 22;

@@ -1952,7 +1952,7 @@ __global__ __launch_bounds__(256) void k_backproject_win(const float *__restrict
 // buffers.  The copies for the next pair are issued before this pair's
 // MFMAs.  Two block barriers per pair: windows staged, Q handed over.
 // ---------------------------------------------------------------------------
-template <int UP, int MT, bool BF16>
+template <int UP, int MT, bool BF16, bool JOS>
 __global__ __launch_bounds__(256) void k_backproject_pw(const float *__restrict__ yf,
                                                         const ProjFrame *__restrict__ frames,
                                                         const float *__restrict__ Bu, const s4 *__restrict__ BuT16,
@@ -2002,8 +2002,9 @@ __global__ __launch_bounds__(256) void k_backproject_pw(const float *__restrict_
             bmin += (ka >= 0.0 ? lo - f.o[a] : hi - f.o[a]) * ka;
             bmax += (ka >= 0.0 ? hi - f.o[a] : lo - f.o[a]) * ka;
         }
-        const int ja = max(0, (int)ceil(amin - f.lj) - 1), jb = min(nj - 1, (int)floor(amax + f.lj) + 1);
-        const int ka0 = max(0, (int)ceil(bmin - f.lk) - 1), kb = min(nk - 1, (int)floor(bmax + f.lk) + 1);
+        const double rj = JOS ? (double)f.jos_rj : f.lj, rk = JOS ? (double)f.jos_rk : f.lk;
+        const int ja = max(0, (int)ceil(amin - rj) - 1), jb = min(nj - 1, (int)floor(amax + rj) + 1);
+        const int ka0 = max(0, (int)ceil(bmin - rk) - 1), kb = min(nk - 1, (int)floor(bmax + rk) + 1);
         j0 = __builtin_amdgcn_readfirstlane(ja);
         k0 = __builtin_amdgcn_readfirstlane(ka0);
         nr = __builtin_amdgcn_readfirstlane(max(0, min(WR, jb - ja + 1)));
@@ -2100,68 +2101,122 @@ __global__ __launch_bounds__(256) void k_backproject_pw(const float *__restrict_
         __syncthreads();  // this pair's windows are staged
         if (has_own && valid) {
             const ProjFrame &f = frames[s_own];
-            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
-            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
-            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
-            const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
-            const double af = floor(a), bf = floor(bb), tf = floor(ts);
-            const int ai = (int)af, bi = (int)bf;
-            const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
-            const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
-            float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
-            asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
-            float dfv[3] = {f.df[0], f.df[1], f.df[2]};
-            asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
-            const float ljf = (float)f.lj;
-            const int jlo = max(wj0, ai + (int)ceilf(ar - ljf));
-            const int jhi = min(wj0 + wnr - 1, ai + (int)floorf(ar + ljf));
-            const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
-            const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
-            for (int j = jlo; j <= jhi; ++j) {
-                const float dj = (float)(j - ai) - ar;
-                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
-                                         fmaf(f.hull[4], dj, cu[2]));
-                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
-                                         fmaf(f.hull[10], dj, cl[2]));
-                const int klo = max(wk0, bi + (int)ceilf(zmin));
-                const int khi = min(wk0 + wnc - 1, bi + (int)floorf(zmax));
-                const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
-                const int rowoff = (j - wj0) * WROW - wk0 * Q;
-                const f4 *wo = win_own + rowoff, *wr = win_ref + rowoff;
-                float dk = (float)(klo - bi) - br;
-                for (int k = klo; k <= khi; ++k, dk += 1.0f) {
-                    f4 yv[Q], ym[Q];
+            if constexpr (JOS) {
+                // Joseph's method: the rays whose cut with the voxel's layer lies
+                // within one voxel in-plane, weight (1 - |Delta_B|)(1 - |Delta_C|) /
+                // |d_A|.  The inverse voxel's cut of the reflected ray is the negated
+                // cut point, so the same weight serves both voxels of the pair.
+                const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+                const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+                const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+                const double af = floor(a), bf = floor(bb);
+                const int ai = (int)af, bi = (int)bf;
+                const float ar = (float)(a - af), br = (float)(bb - bf);
+                const float gjB = f.jos_gj[0], gjC = f.jos_gj[1], gkB = f.jos_gk[0], gkC = f.jos_gk[1];
+                const int jlo = max(wj0, ai + (int)ceilf(ar - f.jos_rj));
+                const int jhi = min(wj0 + wnr - 1, ai + (int)floorf(ar + f.jos_rj));
+                for (int j = jlo; j <= jhi; ++j) {
+                    const float dj = (float)(j - ai) - ar;
+                    const float eB = dj * gjB, eC = dj * gjC;
+                    // dk range with |dk gk + e| < 1 on both in-plane axes (a flat
+                    // axis gives all dk or none; the other one is never flat)
+                    const float xB1 = (-1.0f - eB) * f.jos_igk[0], xB2 = (1.0f - eB) * f.jos_igk[0];
+                    const float xC1 = (-1.0f - eC) * f.jos_igk[1], xC2 = (1.0f - eC) * f.jos_igk[1];
+                    const float lo = fmaxf(fminf(xB1, xB2), fminf(xC1, xC2));
+                    const float hi = fminf(fmaxf(xB1, xB2), fmaxf(xC1, xC2));
+                    if (!(lo < hi)) continue;
+                    const int klo = max(wk0, bi + (int)ceilf(br + lo - 1e-4f));
+                    const int khi = min(wk0 + wnc - 1, bi + (int)floorf(br + hi + 1e-4f));
+                    const int rowoff = (j - wj0) * WROW - wk0 * Q;
+                    const f4 *wo = win_own + rowoff, *wr = win_ref + rowoff;
+                    for (int k = klo; k <= khi; ++k) {
+                        f4 yv[Q], ym[Q];
 #pragma unroll
-                    for (int u4 = 0; u4 < Q; ++u4) {
-                        yv[u4] = wo[k * Q + u4];
-                        ym[u4] = wr[k * Q + u4];
-                    }
-                    const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
-                    float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+                        for (int u4 = 0; u4 < Q; ++u4) {
+                            yv[u4] = wo[k * Q + u4];
+                            ym[u4] = wr[k * Q + u4];
+                        }
+                        const float dk = (float)(k - bi) - br;
+                        const float wB = fmaxf(0.0f, 1.0f - fabsf(fmaf(dk, gkB, eB)));
+                        const float wC = fmaxf(0.0f, 1.0f - fabsf(fmaf(dk, gkC, eC)));
+                        const float wt = wB * wC * f.jos_w;
 #pragma unroll
-                    for (int m = 1; m < 3; ++m) {
-                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
-                        thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                        for (int u4 = 0; u4 < UP; u4 += 4) {
+                            q[u4 + 0] = fmaf(wt, yv[u4 / 4].x, q[u4 + 0]);
+                            q[u4 + 1] = fmaf(wt, yv[u4 / 4].y, q[u4 + 1]);
+                            q[u4 + 2] = fmaf(wt, yv[u4 / 4].z, q[u4 + 2]);
+                            q[u4 + 3] = fmaf(wt, yv[u4 / 4].w, q[u4 + 3]);
+                            qm[u4 + 0] = fmaf(wt, ym[u4 / 4].x, qm[u4 + 0]);
+                            qm[u4 + 1] = fmaf(wt, ym[u4 / 4].y, qm[u4 + 1]);
+                            qm[u4 + 2] = fmaf(wt, ym[u4 / 4].z, qm[u4 + 2]);
+                            qm[u4 + 3] = fmaf(wt, ym[u4 / 4].w, qm[u4 + 3]);
+                        }
                     }
-                    float wsum = 0.0f;
-                    const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
-                    const float tend = (m1 - tr + 0.5f) * stepf;
-                    for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
-                        const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
-                        const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
-                        const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
-                        wsum = fmaf(wx * wy, wz, wsum);
-                    }
+                }
+            } else {
+                const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+                const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+                const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+                const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
+                const double af = floor(a), bf = floor(bb), tf = floor(ts);
+                const int ai = (int)af, bi = (int)bf;
+                const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
+                const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
+                float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
+                asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
+                float dfv[3] = {f.df[0], f.df[1], f.df[2]};
+                asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
+                const float ljf = (float)f.lj;
+                const int jlo = max(wj0, ai + (int)ceilf(ar - ljf));
+                const int jhi = min(wj0 + wnr - 1, ai + (int)floorf(ar + ljf));
+                const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
+                const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
+                for (int j = jlo; j <= jhi; ++j) {
+                    const float dj = (float)(j - ai) - ar;
+                    const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
+                                             fmaf(f.hull[4], dj, cu[2]));
+                    const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
+                                             fmaf(f.hull[10], dj, cl[2]));
+                    const int klo = max(wk0, bi + (int)ceilf(zmin));
+                    const int khi = min(wk0 + wnc - 1, bi + (int)floorf(zmax));
+                    const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
+                    const int rowoff = (j - wj0) * WROW - wk0 * Q;
+                    const f4 *wo = win_own + rowoff, *wr = win_ref + rowoff;
+                    float dk = (float)(klo - bi) - br;
+                    for (int k = klo; k <= khi; ++k, dk += 1.0f) {
+                        f4 yv[Q], ym[Q];
 #pragma unroll
-                    for (int u4 = 0; u4 < UP; u4 += 4) {
-                        q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
-                        q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
-                        q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
-                        q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
-                        qm[u4 + 0] = fmaf(wsum, ym[u4 / 4].x, qm[u4 + 0]);
-                        qm[u4 + 1] = fmaf(wsum, ym[u4 / 4].y, qm[u4 + 1]);
-                        qm[u4 + 2] = fmaf(wsum, ym[u4 / 4].z, qm[u4 + 2]);
-                        qm[u4 + 3] = fmaf(wsum, ym[u4 / 4].w, qm[u4 + 3]);
+                        for (int u4 = 0; u4 < Q; ++u4) {
+                            yv[u4] = wo[k * Q + u4];
+                            ym[u4] = wr[k * Q + u4];
+                        }
+                        const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
+                        float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+#pragma unroll
+                        for (int m = 1; m < 3; ++m) {
+                            tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
+                            thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                        }
+                        float wsum = 0.0f;
+                        const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
+                        const float tend = (m1 - tr + 0.5f) * stepf;
+                        for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
+                            const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
+                            const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
+                            const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
+                            wsum = fmaf(wx * wy, wz, wsum);
+                        }
+#pragma unroll
+                        for (int u4 = 0; u4 < UP; u4 += 4) {
+                            q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
+                            q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
+                            q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
+                            q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
+                            qm[u4 + 0] = fmaf(wsum, ym[u4 / 4].x, qm[u4 + 0]);
+                            qm[u4 + 1] = fmaf(wsum, ym[u4 / 4].y, qm[u4 + 1]);
+                            qm[u4 + 2] = fmaf(wsum, ym[u4 / 4].z, qm[u4 + 2]);
+                            qm[u4 + 3] = fmaf(wsum, ym[u4 / 4].w, qm[u4 + 3]);
+                        }
                     }
                 }
             }
@@ -2219,12 +2274,16 @@ __global__ __launch_bounds__(256) void k_backproject_pw(const float *__restrict_
 // Window extent (rows, columns) of a voxel box with centre spans (sx, sy, sz)
 // over the projections: span . |e| + 2 l + 3 (L1 reach on both sides and the
 // rounding margins); 0 if some projection exceeds lim.
-static void window_extent(const std::vector<ProjFrame> &frames, double sx, double sy, double sz, int &wr, int &wc)
+static void window_extent(const std::vector<ProjFrame> &frames, double sx, double sy, double sz, bool jos, int &wr,
+                          int &wc)
 {
     wr = wc = 0;
     for (const ProjFrame &f : frames) {
-        const double sj = sx * fabs(f.ej[0]) + sy * fabs(f.ej[1]) + sz * fabs(f.ej[2]) + 2 * f.lj;
-        const double sk = sx * fabs(f.ek[0]) + sy * fabs(f.ek[1]) + sz * fabs(f.ek[2]) + 2 * f.lk;
+        // reach of one voxel's rays: the L1 radius of the trilinear support, or
+        // the parallelogram of Joseph cuts within one voxel
+        const double rj = jos ? (double)f.jos_rj : f.lj, rk = jos ? (double)f.jos_rk : f.lk;
+        const double sj = sx * fabs(f.ej[0]) + sy * fabs(f.ej[1]) + sz * fabs(f.ej[2]) + 2 * rj;
+        const double sk = sx * fabs(f.ek[0]) + sy * fabs(f.ek[1]) + sz * fabs(f.ek[2]) + 2 * rk;
         wr = std::max(wr, (int)floor(sj) + 3);
         wc = std::max(wc, (int)floor(sk) + 3);
     }
@@ -2232,9 +2291,9 @@ static void window_extent(const std::vector<ProjFrame> &frames, double sx, doubl
 
 // Paired + windowed adjoint: four windows of wr x wc rays x 8 floats beside
 // 18 KiB of Q tiles must leave three blocks per CU (<= 52 KiB per block).
-int backproject_pw_lds(const std::vector<ProjFrame> &frames, int up, int &wr, int &wc)
+int backproject_pw_lds(const std::vector<ProjFrame> &frames, int up, bool jos, int &wr, int &wc)
 {
-    window_extent(frames, 1.0, 7.0, 7.0, wr, wc);
+    window_extent(frames, 1.0, 7.0, 7.0, jos, wr, wc);
     const int bytes = 4 * wr * wc * up * 4;
     return bytes + 2 * 4 * 64 * (up + 1) * 4 <= 52 * 1024 ? bytes : 0;
 }
@@ -2260,7 +2319,7 @@ bool backproject_window_fits(const std::vector<ProjFrame> &frames)
 // unpaired one (5% of it the per-pair barrier), so it is not used there.
 static bool use_inv_pair(const Dims &d) { return d.inv_pair && !d.joseph && d.Up == 4; }
 static bool use_window(const Dims &d) { return d.win_ok && !d.joseph && d.Up == 8; }
-static bool use_pw(const Dims &d) { return d.pw_lds > 0 && d.inv_pair && !d.joseph && d.Up == 8; }
+static bool use_pw(const Dims &d) { return (d.joseph ? d.pwj_lds : d.pw_lds) > 0 && d.inv_pair && d.Up == 8; }
 static int backproject_inv_blocks(const Dims &d) { return ((d.nx / 2 + 1) / 2) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
 
 int backproject_blocks(const Dims &d)
@@ -2288,14 +2347,21 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
     }
     if constexpr (UP == 8) {
         if (use_pw(d)) {
-            if (bf16)
-                hipLaunchKernelGGL((k_backproject_pw<UP, MT, true>), grid, block, d.pw_lds, st, yf, frames, Bu, bt,
-                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, d.pw_wr,
-                                   d.pw_wc);
+            // residual windows sized for the model's reach
+            const int lds = d.joseph ? d.pwj_lds : d.pw_lds;
+            const int wr = d.joseph ? d.pwj_wr : d.pw_wr, wc = d.joseph ? d.pwj_wc : d.pw_wc;
+            if (bf16 && d.joseph)
+                hipLaunchKernelGGL((k_backproject_pw<UP, MT, true, true>), grid, block, lds, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, wr, wc);
+            else if (bf16)
+                hipLaunchKernelGGL((k_backproject_pw<UP, MT, true, false>), grid, block, lds, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, wr, wc);
+            else if (d.joseph)
+                hipLaunchKernelGGL((k_backproject_pw<UP, MT, false, true>), grid, block, lds, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, wr, wc);
             else
-                hipLaunchKernelGGL((k_backproject_pw<UP, MT, false>), grid, block, d.pw_lds, st, yf, frames, Bu, bt,
-                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, d.pw_wr,
-                                   d.pw_wc);
+                hipLaunchKernelGGL((k_backproject_pw<UP, MT, false, false>), grid, block, lds, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials, wr, wc);
             return hipGetLastError();
         }
         if (use_window(d)) {
