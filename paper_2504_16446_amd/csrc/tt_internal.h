@@ -87,8 +87,8 @@ struct Dims {
     int march_lds;      // dynamic LDS bytes of the staged march (0: no projection staged)
     int joseph;         // 0: unit-step trilinear samples, 1: Joseph's method
     int inv_pair;       // 1: point-inversion-symmetric geometry (no detector offsets, even nx):
-                        //    the trilinear adjoint with four unique segments enumerates each
-                        //    voxel pair (v, -v) once
+                        //    the adjoint (either model) with four or eight unique segments
+                        //    enumerates each voxel pair (v, -v) once
     int win_ok;         // 1: every projection's residual window of a 4 x 8 x 8 brick fits the
                         //    adjoint's LDS window (trilinear model, eight unique segments)
     int pw_lds, pw_wr, pw_wc;  // paired + windowed adjoint: dynamic LDS bytes (0: not used) and

@@ -1478,7 +1478,7 @@ __global__ __launch_bounds__(256) void k_backproject(const float *__restrict__ y
 // Q with B^T on MFMA into its own accumulators.  Enumeration work per voxel
 // and projection is halved; the transpose maps are unchanged.
 // ---------------------------------------------------------------------------
-template <int UP, int MT, bool BF16>
+template <int UP, int MT, bool BF16, bool JOS>
 __global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict__ yf,
                                                          const ProjFrame *__restrict__ frames,
                                                          const float *__restrict__ Bu, const s4 *__restrict__ BuT16,
@@ -1572,73 +1572,129 @@ __global__ __launch_bounds__(256) void k_backproject_inv(const float *__restrict
         for (int u = 0; u < UP; ++u) q[u] = qm[u] = 0.0f;
         if (has_own && valid) {
             const ProjFrame &f = frames[s_own];
-            // voxel centre in the ray frame (float64), split into integer + fraction
-            const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
-            const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
-            const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
-            const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
-            const double af = floor(a), bf = floor(bb), tf = floor(ts);
-            const int ai = (int)af, bi = (int)bf;
-            const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
-            const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
-            float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
-            asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
-            // the sample step in vector registers: reloading it from the frame per
-            // ray (scalar pressure) made each ray wait on the scalar load
-            float dfv[3] = {f.df[0], f.df[1], f.df[2]};
-            asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
-            const float ljf = (float)f.lj;
-            const int jlo = max(0, ai + (int)ceilf(ar - ljf));
-            const int jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
-            const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
-            const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
-            const f4 *ys = reinterpret_cast<const f4 *>(yf + (long long)s_own * nj * nk * UP);
-            for (int j = jlo; j <= jhi; ++j) {
-                const float dj = (float)(j - ai) - ar;
-                const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
-                                         fmaf(f.hull[4], dj, cu[2]));
-                const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
-                                         fmaf(f.hull[10], dj, cl[2]));
-                const int klo = max(0, bi + (int)ceilf(zmin));
-                const int khi = min(nk - 1, bi + (int)floorf(zmax));
-                const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
-                const f4 *yrow = ys + __umul24(j, nk * (UP / 4));
-                // mirrored ray (nj-1-j, nk-1-k): row nj-1-j read backwards from column nk-1
-                const f4 *yrowm = ys + __umul24(nj - 1 - j, nk * (UP / 4)) + (nk - 1) * (UP / 4);
-                float dk = (float)(klo - bi) - br;
-                for (int k = klo; k <= khi; ++k, dk += 1.0f) {
-                    f4 yv[UP / 4], ym[UP / 4];
+            if constexpr (JOS) {
+                // Joseph's method: the rays whose cut with the voxel's layer lies
+                // within one voxel in-plane, weight (1 - |Delta_B|)(1 - |Delta_C|) /
+                // |d_A|; the inverse voxel's cut of the mirrored ray is the negated
+                // cut point, so the same weight serves both voxels of the pair
+                const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+                const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+                const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+                const double af = floor(a), bf = floor(bb);
+                const int ai = (int)af, bi = (int)bf;
+                const float ar = (float)(a - af), br = (float)(bb - bf);
+                const float gjB = f.jos_gj[0], gjC = f.jos_gj[1], gkB = f.jos_gk[0], gkC = f.jos_gk[1];
+                const int jlo = max(0, ai + (int)ceilf(ar - f.jos_rj));
+                const int jhi = min(nj - 1, ai + (int)floorf(ar + f.jos_rj));
+                const f4 *ys = reinterpret_cast<const f4 *>(yf + (long long)s_own * nj * nk * UP);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const float dj = (float)(j - ai) - ar;
+                    const float eB = dj * gjB, eC = dj * gjC;
+                    // dk range with |dk gk + e| < 1 on both in-plane axes (a flat
+                    // axis gives all dk or none; the other one is never flat)
+                    const float xB1 = (-1.0f - eB) * f.jos_igk[0], xB2 = (1.0f - eB) * f.jos_igk[0];
+                    const float xC1 = (-1.0f - eC) * f.jos_igk[1], xC2 = (1.0f - eC) * f.jos_igk[1];
+                    const float lo = fmaxf(fminf(xB1, xB2), fminf(xC1, xC2));
+                    const float hi = fminf(fmaxf(xB1, xB2), fmaxf(xC1, xC2));
+                    if (!(lo < hi)) continue;
+                    const int klo = max(0, bi + (int)ceilf(br + lo - 1e-4f));
+                    const int khi = min(nk - 1, bi + (int)floorf(br + hi + 1e-4f));
+                    const f4 *yrow = ys + __umul24(j, nk * (UP / 4));
+                    // mirrored ray (nj-1-j, nk-1-k): row nj-1-j read backwards from column nk-1
+                    const f4 *yrowm = ys + __umul24(nj - 1 - j, nk * (UP / 4)) + (nk - 1) * (UP / 4);
+                    for (int k = klo; k <= khi; ++k) {
+                        f4 yv[UP / 4], ym[UP / 4];
 #pragma unroll
-                    for (int u4 = 0; u4 < UP / 4; ++u4) {
-                        yv[u4] = yrow[k * (UP / 4) + u4];
-                        ym[u4] = yrowm[u4 - k * (UP / 4)];
-                    }
-                    const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
-                    float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+                        for (int u4 = 0; u4 < UP / 4; ++u4) {
+                            yv[u4] = yrow[k * (UP / 4) + u4];
+                            ym[u4] = yrowm[u4 - k * (UP / 4)];
+                        }
+                        const float dk = (float)(k - bi) - br;
+                        const float wB = fmaxf(0.0f, 1.0f - fabsf(fmaf(dk, gkB, eB)));
+                        const float wC = fmaxf(0.0f, 1.0f - fabsf(fmaf(dk, gkC, eC)));
+                        const float wt = wB * wC * f.jos_w;
 #pragma unroll
-                    for (int m = 1; m < 3; ++m) {
-                        tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
-                        thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                        for (int u4 = 0; u4 < UP; u4 += 4) {
+                            q[u4 + 0] = fmaf(wt, yv[u4 / 4].x, q[u4 + 0]);
+                            q[u4 + 1] = fmaf(wt, yv[u4 / 4].y, q[u4 + 1]);
+                            q[u4 + 2] = fmaf(wt, yv[u4 / 4].z, q[u4 + 2]);
+                            q[u4 + 3] = fmaf(wt, yv[u4 / 4].w, q[u4 + 3]);
+                            qm[u4 + 0] = fmaf(wt, ym[u4 / 4].x, qm[u4 + 0]);
+                            qm[u4 + 1] = fmaf(wt, ym[u4 / 4].y, qm[u4 + 1]);
+                            qm[u4 + 2] = fmaf(wt, ym[u4 / 4].z, qm[u4 + 2]);
+                            qm[u4 + 3] = fmaf(wt, ym[u4 / 4].w, qm[u4 + 3]);
+                        }
                     }
-                    float wsum = 0.0f;
-                    const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
-                    const float tend = (m1 - tr + 0.5f) * stepf;
-                    for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
-                        const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
-                        const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
-                        const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
-                        wsum = fmaf(wx * wy, wz, wsum);
-                    }
+                }
+            } else {
+                // voxel centre in the ray frame (float64), split into integer + fraction
+                const double w0 = xv[0] - f.o[0], w1 = xv[1] - f.o[1], w2 = xv[2] - f.o[2];
+                const double a = w0 * f.ej[0] + w1 * f.ej[1] + w2 * f.ej[2];
+                const double bb = w0 * f.ek[0] + w1 * f.ek[1] + w2 * f.ek[2];
+                const double ts = (w0 * f.d[0] + w1 * f.d[1] + w2 * f.d[2]) * inv_step;
+                const double af = floor(a), bf = floor(bb), tf = floor(ts);
+                const int ai = (int)af, bi = (int)bf;
+                const float ar = (float)(a - af), br = (float)(bb - bf), tr = (float)(ts - tf);
+                const float hinv[3] = {fabsf(f.inv_df[0]), fabsf(f.inv_df[1]), fabsf(f.inv_df[2])};
+                float nhv[3] = {-hinv[0], -hinv[1], -hinv[2]};
+                asm volatile("" : "+v"(nhv[0]), "+v"(nhv[1]), "+v"(nhv[2]));
+                // the sample step in vector registers: reloading it from the frame per
+                // ray (scalar pressure) made each ray wait on the scalar load
+                float dfv[3] = {f.df[0], f.df[1], f.df[2]};
+                asm volatile("" : "+v"(dfv[0]), "+v"(dfv[1]), "+v"(dfv[2]));
+                const float ljf = (float)f.lj;
+                const int jlo = max(0, ai + (int)ceilf(ar - ljf));
+                const int jhi = min(nj - 1, ai + (int)floorf(ar + ljf));
+                const float cu[3] = {f.hull[1] + (br + 1e-4f), f.hull[3] + (br + 1e-4f), f.hull[5] + (br + 1e-4f)};
+                const float cl[3] = {f.hull[7] + (br - 1e-4f), f.hull[9] + (br - 1e-4f), f.hull[11] + (br - 1e-4f)};
+                const f4 *ys = reinterpret_cast<const f4 *>(yf + (long long)s_own * nj * nk * UP);
+                for (int j = jlo; j <= jhi; ++j) {
+                    const float dj = (float)(j - ai) - ar;
+                    const float zmax = fminf(fminf(fmaf(f.hull[0], dj, cu[0]), fmaf(f.hull[2], dj, cu[1])),
+                                             fmaf(f.hull[4], dj, cu[2]));
+                    const float zmin = fmaxf(fmaxf(fmaf(f.hull[6], dj, cl[0]), fmaf(f.hull[8], dj, cl[1])),
+                                             fmaf(f.hull[10], dj, cl[2]));
+                    const int klo = max(0, bi + (int)ceilf(zmin));
+                    const int khi = min(nk - 1, bi + (int)floorf(zmax));
+                    const float pj0 = dj * f.ejf[0], pj1 = dj * f.ejf[1], pj2 = dj * f.ejf[2];
+                    const f4 *yrow = ys + __umul24(j, nk * (UP / 4));
+                    // mirrored ray (nj-1-j, nk-1-k): row nj-1-j read backwards from column nk-1
+                    const f4 *yrowm = ys + __umul24(nj - 1 - j, nk * (UP / 4)) + (nk - 1) * (UP / 4);
+                    float dk = (float)(klo - bi) - br;
+                    for (int k = klo; k <= khi; ++k, dk += 1.0f) {
+                        f4 yv[UP / 4], ym[UP / 4];
 #pragma unroll
-                    for (int u4 = 0; u4 < UP; u4 += 4) {
-                        q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
-                        q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
-                        q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
-                        q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
-                        qm[u4 + 0] = fmaf(wsum, ym[u4 / 4].x, qm[u4 + 0]);
-                        qm[u4 + 1] = fmaf(wsum, ym[u4 / 4].y, qm[u4 + 1]);
-                        qm[u4 + 2] = fmaf(wsum, ym[u4 / 4].z, qm[u4 + 2]);
-                        qm[u4 + 3] = fmaf(wsum, ym[u4 / 4].w, qm[u4 + 3]);
+                        for (int u4 = 0; u4 < UP / 4; ++u4) {
+                            yv[u4] = yrow[k * (UP / 4) + u4];
+                            ym[u4] = yrowm[u4 - k * (UP / 4)];
+                        }
+                        const float P[3] = {fmaf(dk, f.ekf[0], pj0), fmaf(dk, f.ekf[1], pj1), fmaf(dk, f.ekf[2], pj2)};
+                        float tlo = fmaf(-P[0], f.inv_df[0], nhv[0]), thi = fmaf(-P[0], f.inv_df[0], hinv[0]);
+#pragma unroll
+                        for (int m = 1; m < 3; ++m) {
+                            tlo = fmaxf(tlo, fmaf(-P[m], f.inv_df[m], nhv[m]));
+                            thi = fminf(thi, fmaf(-P[m], f.inv_df[m], hinv[m]));
+                        }
+                        float wsum = 0.0f;
+                        const float m0 = ceilf(fmaf(tlo, inv_stepf, tr)), m1 = floorf(fmaf(thi, inv_stepf, tr));
+                        const float tend = (m1 - tr + 0.5f) * stepf;
+                        for (float tau = (m0 - tr) * stepf; tau < tend; tau += stepf) {
+                            const float wx = 1.0f - fabsf(fmaf(tau, dfv[0], P[0]));
+                            const float wy = 1.0f - fabsf(fmaf(tau, dfv[1], P[1]));
+                            const float wz = 1.0f - fabsf(fmaf(tau, dfv[2], P[2]));
+                            wsum = fmaf(wx * wy, wz, wsum);
+                        }
+#pragma unroll
+                        for (int u4 = 0; u4 < UP; u4 += 4) {
+                            q[u4 + 0] = fmaf(wsum, yv[u4 / 4].x, q[u4 + 0]);
+                            q[u4 + 1] = fmaf(wsum, yv[u4 / 4].y, q[u4 + 1]);
+                            q[u4 + 2] = fmaf(wsum, yv[u4 / 4].z, q[u4 + 2]);
+                            q[u4 + 3] = fmaf(wsum, yv[u4 / 4].w, q[u4 + 3]);
+                            qm[u4 + 0] = fmaf(wsum, ym[u4 / 4].x, qm[u4 + 0]);
+                            qm[u4 + 1] = fmaf(wsum, ym[u4 / 4].y, qm[u4 + 1]);
+                            qm[u4 + 2] = fmaf(wsum, ym[u4 / 4].z, qm[u4 + 2]);
+                            qm[u4 + 3] = fmaf(wsum, ym[u4 / 4].w, qm[u4 + 3]);
+                        }
                     }
                 }
             }
@@ -2317,7 +2373,7 @@ bool backproject_window_fits(const std::vector<ProjFrame> &frames)
 // to 102 (three waves per SIMD instead of four) and the kernel, then bound by
 // load latency rather than by VALU issue, measured 10% slower than the
 // unpaired one (5% of it the per-pair barrier), so it is not used there.
-static bool use_inv_pair(const Dims &d) { return d.inv_pair && !d.joseph && d.Up == 4; }
+static bool use_inv_pair(const Dims &d) { return d.inv_pair && d.Up == 4; }
 static bool use_window(const Dims &d) { return d.win_ok && !d.joseph && d.Up == 8; }
 static bool use_pw(const Dims &d) { return (d.joseph ? d.pwj_lds : d.pw_lds) > 0 && d.inv_pair && d.Up == 8; }
 static int backproject_inv_blocks(const Dims &d) { return ((d.nx / 2 + 1) / 2) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8); }
@@ -2336,12 +2392,18 @@ static hipError_t bp_t(const Dims &d, const ProjFrame *frames, const float *yf, 
     const dim3 grid(backproject_blocks(d)), block(256);
     if constexpr (UP == 4) {
         if (use_inv_pair(d)) {
-            if (bf16)
-                hipLaunchKernelGGL((k_backproject_inv<UP, MT, true>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
-                                   d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            if (bf16 && d.joseph)
+                hipLaunchKernelGGL((k_backproject_inv<UP, MT, true, true>), grid, block, 0, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            else if (bf16)
+                hipLaunchKernelGGL((k_backproject_inv<UP, MT, true, false>), grid, block, 0, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+            else if (d.joseph)
+                hipLaunchKernelGGL((k_backproject_inv<UP, MT, false, true>), grid, block, 0, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
             else
-                hipLaunchKernelGGL((k_backproject_inv<UP, MT, false>), grid, block, 0, st, yf, frames, Bu, bt, d.S,
-                                   d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
+                hipLaunchKernelGGL((k_backproject_inv<UP, MT, false, false>), grid, block, 0, st, yf, frames, Bu, bt,
+                                   d.S, d.nx, d.ny, d.nz, d.nj, d.nk, d.C, d.Cp, d.step, g, beta, c, partials);
             return hipGetLastError();
         }
     }
